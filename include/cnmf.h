@@ -1,0 +1,212 @@
+/*
+ * cnmf.h -- C ABI of the MI355X (gfx950) compressed-NeNMF library.
+ *
+ * Method: F. Yahaya, M. Puigt, G. Delmaire, G. Roussel, "Faster-than-fast NMF
+ * using random projections and Nesterov iterations" (arXiv 1812.04315).
+ *
+ *   NMF model X ~ G F with X (n x m) >= 0, G (n x p) >= 0, F (p x m) >= 0:
+ *     Sec. 1, Eq. (1); alternating subproblems Eqs. (2) and (3).
+ *   NeNMF inner loop (Nesterov optimal gradient): Sec. 2.
+ *   Compressed NMF strategy: Sec. 3, Algorithm 1.
+ *   Randomized subspace iteration: Sec. 3, Algorithm 2.
+ *   Relative reconstruction error: Sec. 4, Eq. (4).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are row-major.  "ld" is the row pitch in elements (>= columns).
+ *   - Every array pointer is a caller-owned DEVICE pointer on the context's
+ *     device, unless the comment says "host".  The library never frees,
+ *     retains or reallocates caller memory.  Scratch lives in the context.
+ *   - Calls are asynchronous: they validate arguments on the host, enqueue
+ *     kernels on the context's HIP stream and return.  Argument errors are
+ *     returned synchronously; errors found by the kernels (non-finite or
+ *     negative data, a basis that cannot be completed, a stalled grid
+ *     barrier) are OR-ed into a device status word read by cnmf_status().
+ *   - Return value: CNMF_OK (0) or a negative CNMF_E* code.
+ *   - One context per stream; a context is not thread-safe.
+ */
+#ifndef CNMF_H
+#define CNMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes --------------------------------------------------- */
+#define CNMF_OK          0
+#define CNMF_EINVAL     -1   /* bad argument: shape, limit, NULL, alignment   */
+#define CNMF_ENOMEM     -2   /* workspace allocation failed                    */
+#define CNMF_EHIP       -3   /* a HIP runtime call failed                      */
+#define CNMF_EDEVICE    -4   /* cnmf_status(): the device status word is set   */
+
+/* ---- device status word bits (cnmf_status) ----------------------------- */
+#define CNMF_ST_NONFINITE   0x01  /* NaN/Inf met in data, a Gram or a norm     */
+#define CNMF_ST_NEGATIVE    0x02  /* X has a negative entry (validation pass)  */
+#define CNMF_ST_BREAKDOWN   0x04  /* replacement basis column also deficient   */
+#define CNMF_ST_ZERO_LIPS   0x08  /* warning: W = 0, factor left unchanged     */
+#define CNMF_ST_TIMEOUT     0x10  /* a grid barrier stalled; results invalid   */
+
+/* ---- limits ---------------------------------------------------------- */
+#define CNMF_MAX_RANK    32   /* p and l = p + nu are at most 32              */
+
+/* ---- parameters ------------------------------------------------------ */
+#define CNMF_STOP_GLOBAL      0  /* tol = ratio * ||(P grad_G, P grad_F)|| at (G0,F0); /10 rule */
+#define CNMF_STOP_SUBPROBLEM  1  /* tol = ratio * ||P grad(Z_0)|| per inner loop              */
+
+#define CNMF_PREC_FP32  0
+#define CNMF_PREC_BF16  1
+
+#define CNMF_FLAG_VALIDATE_INPUT  0x1  /* check X finite and >= 0 before the sketch */
+
+#define CNMF_METHOD_PLAIN       0  /* NeNMF on X (Sec. 2)                   */
+#define CNMF_METHOD_COMPRESSED  1  /* NeNMF on X_L, X_R (Algorithm 1)       */
+
+typedef struct cnmf_params {
+    int32_t p;            /* factorisation rank, 1 <= p <= 32 (Eq. (1))                */
+    int32_t nu;           /* oversampling: sketch width l = p + nu, l <= min(n,m), <= 32;
+                             the paper's target rank (Sec. 3) is l                      */
+    int32_t q;            /* power iterations of Algorithm 2, q >= 1                    */
+    int32_t outer_iters;  /* outer (alternating) iterations T >= 0                      */
+    int32_t inner_max;    /* Max_iter of the inner loop (Sec. 2), 1..100000             */
+    int32_t inner_min;    /* earliest step at which the gradient bound is tested, >= 1  */
+    double  inner_ratio;  /* gradient-bound ratio (e.g. 1e-3)                           */
+    double  tau2;         /* numerical-rank threshold of the orthonormalisation (1e-9)  */
+    int32_t stop_rule;    /* CNMF_STOP_*                                                */
+    int32_t sweep_prec;   /* CNMF_PREC_*: arithmetic of the X-sized sweeps              */
+    int32_t flags;        /* CNMF_FLAG_*                                                */
+    int32_t reserved;     /* must be 0                                                  */
+} cnmf_params;
+
+/* Fills p = 0 ... with the library defaults (q = 4, inner_max = 500,
+ * inner_min = 1, inner_ratio = 1e-3, tau2 = 1e-9, global stop, FP32). */
+void cnmf_params_default(cnmf_params* out);
+
+/* Optional per-outer-iteration trace of cnmf_solve.  Every pointer is a
+ * device pointer or NULL.  T = outer_iters. */
+typedef struct cnmf_trace {
+    int32_t*  steps;   /* T x 2: inner steps taken (G update, F update)            */
+    double*   lips;    /* T x 2: Lipschitz constants used                           */
+    double*   tols;    /* T x 2: gradient bound in force                            */
+    uint64_t* ticks;   /* T + 1: device wall clock (cnmf_clock_hz) at the start and
+                          at the end of every outer iteration                        */
+    float*    G_hist;  /* T x n x p: G after every outer iteration                  */
+    float*    F_hist;  /* T x p x m: F after every outer iteration                  */
+} cnmf_trace;
+
+typedef struct cnmf_ctx cnmf_ctx;
+
+/* ---- context --------------------------------------------------------- */
+
+/* Creates a context on HIP device `device`, enqueuing on `stream` (a
+ * hipStream_t; NULL = the null stream).  *out receives the handle. */
+int cnmf_create(cnmf_ctx** out, int device, void* stream);
+int cnmf_destroy(cnmf_ctx* ctx);
+int cnmf_set_stream(cnmf_ctx* ctx, void* stream);
+/* Frequency in Hz of the device clock written to cnmf_trace.ticks. */
+int cnmf_clock_hz(cnmf_ctx* ctx, double* hz_out /* host */);
+/* Waits for the stream, returns the status word in *status (host) and
+ * clears it.  Returns CNMF_EDEVICE when any error bit (not the zero-
+ * Lipschitz warning) was set. */
+int cnmf_status(cnmf_ctx* ctx, int32_t* status /* host */);
+const char* cnmf_strerror(int code);
+
+/* ---- the hot path ---------------------------------------------------- */
+
+/* Randomized subspace iteration, Sec. 3, Algorithm 2, l = p + nu.
+ *   X        n x m (ldx), >= 0.
+ *   omega_L  m x l Gaussian (Algorithm 2's Omega_L), row-major, ld = l.
+ *   omega_R  l x n Gaussian (Algorithm 2's Omega_R), row-major, ld = n.
+ *   Q_L      out, n x l, orthonormal columns, basis of (X X^T)^q Omega_R^T.
+ *   Q_R      out, m x l, orthonormal columns, basis of (X^T X)^q Omega_L.
+ *   X_L      out, l x m = Q_L^T X   (Algorithm 1's L X).
+ *   X_R      out, n x l = X Q_R     (Algorithm 1's X R).
+ * Two independent chains, re-orthonormalised at every half-step by
+ * CholeskyQR2 with FP64 Gram and Cholesky.  A column whose Cholesky pivot
+ * is <= tau2 * max_j ||y_j||^2 is replaced by the same column of the other
+ * Gaussian draw (Omega_R^T for n-space panels, Omega_L for m-space panels).
+ * Sweeps run in FP32 (sweep_prec must be CNMF_PREC_FP32 here). */
+int cnmf_rsi(cnmf_ctx* ctx, int64_t n, int64_t m, const float* X, int64_t ldx,
+             const cnmf_params* prm, const float* omega_L, const float* omega_R,
+             float* Q_L, float* Q_R, float* X_L, float* X_R);
+
+/* Same, with the X-sized sweeps in BF16 on MFMA (FP32 accumulation):
+ *   Xb  n x m (ldxb) bfloat16 bit patterns of X (see cnmf_to_bf16).
+ * Gram, Cholesky and outputs as cnmf_rsi; X_L, X_R are computed from Xb. */
+int cnmf_rsi_bf16(cnmf_ctx* ctx, int64_t n, int64_t m, const uint16_t* Xb,
+                  int64_t ldxb, const cnmf_params* prm, const float* omega_L,
+                  const float* omega_R, float* Q_L, float* Q_R, float* X_L,
+                  float* X_R);
+
+/* Round X (n x m, ldx) to bfloat16 (round to nearest even) into Xb (ldxb). */
+int cnmf_to_bf16(cnmf_ctx* ctx, int64_t n, int64_t m, const float* X,
+                 int64_t ldx, uint16_t* Xb, int64_t ldxb);
+
+/* NeNMF outer loop: plain (Sec. 2, needs X) or compressed (Algorithm 1,
+ * needs Q_L, Q_R, X_L, X_R from cnmf_rsi; X may then be NULL).
+ *   G  in/out n x p (ld = p), F in/out p x m (ld = m); G0, F0 >= 0.
+ *   trace  optional (host struct of device pointers), may be NULL.
+ *   replay optional device int32 T x 2: run exactly these inner step counts
+ *          instead of testing the gradient bound (parity runs).
+ * Per outer iteration: G update on Eq. (2) (or its compressed form), then F
+ * update on Eq. (3), each by one Nesterov inner loop with step 1/L,
+ * L = lambda_max(W) in FP64, projected gradient norms in FP64. */
+int cnmf_solve(cnmf_ctx* ctx, int method, int64_t n, int64_t m,
+               const float* X, int64_t ldx,
+               const float* Q_L, const float* Q_R, const float* X_L,
+               const float* X_R, const cnmf_params* prm, float* G, float* F,
+               const cnmf_trace* trace, const int32_t* replay);
+
+/* Relative reconstruction error, Sec. 4, Eq. (4), for `count` factor pairs
+ * G_i = G + i*strideG, F_i = F + i*strideF (element strides):
+ *   out[i] = ||X - G_i F_i||_F / ||X||_F   (device double[count]).
+ * Direct residual with FP64 accumulation. */
+int cnmf_rre(cnmf_ctx* ctx, int64_t n, int64_t m, const float* X, int64_t ldx,
+             int32_t p, const float* G, int64_t strideG, const float* F,
+             int64_t strideF, int32_t count, double* out);
+
+/* ---- kernel-level entry points (the steps above, one at a time) ------ */
+
+/* Y (R x k, ldy) = X (R x C, ldx) * A, where A is C x k (a_trans = 0,
+ * row pitch lda) or is given as its transpose k x C (a_trans = 1).
+ * FP32 MFMA, FP32 accumulation.  k <= 32. */
+int cnmf_sweep_right(cnmf_ctx* ctx, int64_t R, int64_t C, const float* X,
+                     int64_t ldx, int32_t k, const float* A, int64_t lda,
+                     int32_t a_trans, float* Y, int64_t ldy);
+
+/* Z = X^T (C x R) * B (R x k, ldb): written C x k (z_trans = 0) or as its
+ * transpose k x C (z_trans = 1), row pitch ldz.  FP32 MFMA.  k <= 32. */
+int cnmf_sweep_left(cnmf_ctx* ctx, int64_t R, int64_t C, const float* X,
+                    int64_t ldx, int32_t k, const float* B, int64_t ldb,
+                    float* Z, int64_t ldz, int32_t z_trans);
+
+/* Orthonormal basis of Y (N x l, ld = l) by CholeskyQR2 with the rank rule
+ * of cnmf_rsi; pool is N x l (pool_trans = 0, ld = l) or l x N
+ * (pool_trans = 1, ld = N).  Q out N x l.  replaced out: l int32 flags. */
+int cnmf_orth(cnmf_ctx* ctx, int64_t N, int32_t l, const float* Y,
+              const float* pool, int32_t pool_trans, double tau2, float* Q,
+              int32_t* replaced);
+
+/* L = lambda_max(W) of the symmetric p x p FP32 matrix W, FP64
+ * Householder tridiagonalisation and bisection.  out: device double. */
+int cnmf_lipschitz(cnmf_ctx* ctx, int32_t p, const float* W, double* out);
+
+/* One Nesterov inner loop (Sec. 2) on min_{Z>=0} 0.5 tr(Z W Z^T) - tr(B^T Z)
+ * over `rows` independent rows of p unknowns: gradient Z W - B.
+ *   Z  in/out, element (r, c) at Z[r*z_rs + c*z_cs] (G: z_rs = p, z_cs = 1;
+ *      F viewed by columns: z_rs = 1, z_cs = m).
+ *   W  p x p FP32; B rows x p FP32 (ld = p).
+ *   tol      gradient bound (used when forced < 0).
+ *   forced   >= 0: run exactly this many steps.
+ *   steps_out, L_out, pg2_out: device int32 / double / double (may be NULL);
+ *   pg2_out receives ||P grad(Z_0)||^2. */
+int cnmf_nnls(cnmf_ctx* ctx, int64_t rows, int32_t p, float* Z, int64_t z_rs,
+              int64_t z_cs, const float* W, const float* B, double tol,
+              int32_t inner_max, int32_t inner_min, int32_t forced,
+              int32_t* steps_out, double* L_out, double* pg2_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CNMF_H */

@@ -1,0 +1,415 @@
+"""Compressed NeNMF on MI355X (gfx950): thin Python binding of libcnmf.
+
+The work happens in ``libcnmf.so`` (HIP kernels behind the C ABI declared in
+``include/cnmf.h``).  This module only marshals torch tensors (device memory
+and the current HIP stream) into those calls.  There is no fallback: if the
+library is missing or no GPU is present, every entry point raises.
+
+Method: Yahaya, Puigt, Delmaire, Roussel, "Faster-than-fast NMF using random
+projections and Nesterov iterations": randomized subspace iteration
+(Sec. 3, Algorithm 2) feeding compressed NeNMF (Sec. 3, Algorithm 1) whose
+factor updates are NeNMF's Nesterov inner loops (Sec. 2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcnmf.so")
+
+OK, EINVAL, ENOMEM, EHIP, EDEVICE = 0, -1, -2, -3, -4
+ST_NONFINITE, ST_NEGATIVE, ST_BREAKDOWN, ST_ZERO_LIPS, ST_TIMEOUT = 1, 2, 4, 8, 16
+STOP_GLOBAL, STOP_SUBPROBLEM = 0, 1
+PREC_FP32, PREC_BF16 = 0, 1
+FLAG_VALIDATE_INPUT = 1
+METHOD_PLAIN, METHOD_COMPRESSED = 0, 1
+
+EXPORTED = [
+    "cnmf_params_default", "cnmf_strerror", "cnmf_create", "cnmf_destroy",
+    "cnmf_set_stream", "cnmf_clock_hz", "cnmf_status", "cnmf_rsi", "cnmf_rsi_bf16",
+    "cnmf_to_bf16", "cnmf_solve", "cnmf_rre", "cnmf_sweep_right", "cnmf_sweep_left",
+    "cnmf_orth", "cnmf_lipschitz", "cnmf_nnls",
+]
+
+
+class CnmfError(RuntimeError):
+    def __init__(self, code: int, what: str, status: int = 0):
+        super().__init__(f"{what}: {strerror(code)} (code {code}, status 0x{status:x})")
+        self.code = code
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("p", ctypes.c_int32), ("nu", ctypes.c_int32), ("q", ctypes.c_int32),
+        ("outer_iters", ctypes.c_int32), ("inner_max", ctypes.c_int32),
+        ("inner_min", ctypes.c_int32), ("inner_ratio", ctypes.c_double),
+        ("tau2", ctypes.c_double), ("stop_rule", ctypes.c_int32),
+        ("sweep_prec", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_void_p), ("lips", ctypes.c_void_p),
+                ("tols", ctypes.c_void_p), ("ticks", ctypes.c_void_p),
+                ("G_hist", ctypes.c_void_p), ("F_hist", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcnmf.so (built by ``python -m paper_1812_04315_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1812_04315_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        sig = {
+            "cnmf_params_default": (None, [ctypes.POINTER(Params)]),
+            "cnmf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+            "cnmf_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, P]),
+            "cnmf_destroy": (ctypes.c_int, [P]),
+            "cnmf_set_stream": (ctypes.c_int, [P, P]),
+            "cnmf_clock_hz": (ctypes.c_int, [P, ctypes.POINTER(D)]),
+            "cnmf_status": (ctypes.c_int, [P, ctypes.POINTER(I32)]),
+            "cnmf_rsi": (ctypes.c_int, [P, I64, I64, P, I64, ctypes.POINTER(Params), P, P, P, P, P, P]),
+            "cnmf_rsi_bf16": (ctypes.c_int, [P, I64, I64, P, I64, ctypes.POINTER(Params), P, P, P, P, P, P]),
+            "cnmf_to_bf16": (ctypes.c_int, [P, I64, I64, P, I64, P, I64]),
+            "cnmf_solve": (ctypes.c_int, [P, ctypes.c_int, I64, I64, P, I64, P, P, P, P,
+                                          ctypes.POINTER(Params), P, P, ctypes.POINTER(Trace), P]),
+            "cnmf_rre": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, P, I64, I32, P]),
+            "cnmf_sweep_right": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, I32, P, I64]),
+            "cnmf_sweep_left": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, P, I64, I32]),
+            "cnmf_orth": (ctypes.c_int, [P, I64, I32, P, P, I32, D, P, P]),
+            "cnmf_lipschitz": (ctypes.c_int, [P, I32, P, P]),
+            "cnmf_nnls": (ctypes.c_int, [P, I64, I32, P, I64, I64, P, P, D, I32, I32, I32, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().cnmf_strerror(code).decode()
+    except Exception:  # noqa: BLE001
+        return "unknown"
+
+
+def params(p: int, nu: int = 10, q: int = 4, outer_iters: int = 200, inner_max: int = 500,
+           inner_min: int = 1, inner_ratio: float = 1e-3, tau2: float = 1e-9,
+           stop_rule: int = STOP_GLOBAL, sweep_prec: int = PREC_FP32, flags: int = 0) -> Params:
+    return Params(p, nu, q, outer_iters, inner_max, inner_min, inner_ratio, tau2, stop_rule,
+                  sweep_prec, flags, 0)
+
+
+# ---------------------------------------------------------------------------
+# Context (one per device and stream)
+# ---------------------------------------------------------------------------
+_contexts: dict = {}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libcnmf needs a ROCm GPU; none is visible")
+    return torch
+
+
+class Context:
+    def __init__(self, device: int, stream_handle: int):
+        h = ctypes.c_void_p()
+        rc = lib().cnmf_create(ctypes.byref(h), device, ctypes.c_void_p(stream_handle))
+        if rc != OK:
+            raise CnmfError(rc, "cnmf_create")
+        self.h = h
+        self.device = device
+        hz = ctypes.c_double()
+        lib().cnmf_clock_hz(h, ctypes.byref(hz))
+        self.clock_hz = hz.value
+
+    def status(self, clear_ok: bool = True) -> int:
+        st = ctypes.c_int32()
+        rc = lib().cnmf_status(self.h, ctypes.byref(st))
+        if rc not in (OK, EDEVICE):
+            raise CnmfError(rc, "cnmf_status")
+        return st.value
+
+
+def context(device=None):
+    torch = _torch()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    key = (dev, stream)
+    ctx = _contexts.get(key)
+    if ctx is None:
+        ctx = Context(dev, stream)
+        _contexts[key] = ctx
+    return ctx
+
+
+def check(ctx: Context | None = None) -> int:
+    """Synchronise, read and clear the device status word; raise on errors
+    (the zero-Lipschitz warning alone does not raise)."""
+    ctx = ctx or context()
+    st = ctx.status()
+    if st & ~ST_ZERO_LIPS:
+        raise CnmfError(EDEVICE, "device status", st)
+    return st
+
+
+def _call(name: str, *args):
+    rc = getattr(lib(), name)(*args)
+    if rc != OK:
+        raise CnmfError(rc, name)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need(t, dtype, name, shape=None, ld_ok=False):
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.dim() == 2:
+        if t.stride(1) != 1 or (not ld_ok and not t.is_contiguous()):
+            raise ValueError(f"{name} must be row-major" + (" with unit column stride" if ld_ok else " and contiguous"))
+    elif not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    del torch
+
+
+def _ld(t) -> int:
+    return t.stride(0) if t.dim() == 2 else t.shape[-1]
+
+
+# ---------------------------------------------------------------------------
+# Hot path
+# ---------------------------------------------------------------------------
+
+def rsi(X, omega_L, omega_R, p: int, nu: int, q: int = 4, tau2: float = 1e-9,
+        validate: bool = False, out=None):
+    """Randomized subspace iteration (Algorithm 2).  X (n x m, float32, any
+    row pitch), omega_L (m x l), omega_R (l x n).  Returns (Q_L, Q_R, X_L, X_R)."""
+    torch = _torch()
+    n, m = X.shape
+    ell = p + nu
+    _need(X, torch.float32, "X", ld_ok=True)
+    _need(omega_L, torch.float32, "omega_L", (m, ell))
+    _need(omega_R, torch.float32, "omega_R", (ell, n))
+    if out is None:
+        dev = X.device
+        out = (torch.empty(n, ell, device=dev), torch.empty(m, ell, device=dev),
+               torch.empty(ell, m, device=dev), torch.empty(n, ell, device=dev))
+    QL, QR, XL, XR = out
+    prm = params(p, nu, q, tau2=tau2, flags=FLAG_VALIDATE_INPUT if validate else 0)
+    _call("cnmf_rsi", context().h, n, m, _ptr(X), _ld(X), ctypes.byref(prm), _ptr(omega_L),
+          _ptr(omega_R), _ptr(QL), _ptr(QR), _ptr(XL), _ptr(XR))
+    return QL, QR, XL, XR
+
+
+def rsi_bf16(Xb, omega_L, omega_R, p: int, nu: int, q: int = 4, tau2: float = 1e-9, out=None):
+    """Algorithm 2 with the X-sized sweeps in BF16.  Xb is an int16 tensor
+    holding bfloat16 bit patterns (see ``to_bf16``)."""
+    torch = _torch()
+    n, m = Xb.shape
+    ell = p + nu
+    _need(Xb, torch.int16, "Xb", ld_ok=True)
+    _need(omega_L, torch.float32, "omega_L", (m, ell))
+    _need(omega_R, torch.float32, "omega_R", (ell, n))
+    if out is None:
+        dev = Xb.device
+        out = (torch.empty(n, ell, device=dev), torch.empty(m, ell, device=dev),
+               torch.empty(ell, m, device=dev), torch.empty(n, ell, device=dev))
+    QL, QR, XL, XR = out
+    prm = params(p, nu, q, tau2=tau2, sweep_prec=PREC_BF16)
+    _call("cnmf_rsi_bf16", context().h, n, m, _ptr(Xb), _ld(Xb), ctypes.byref(prm),
+          _ptr(omega_L), _ptr(omega_R), _ptr(QL), _ptr(QR), _ptr(XL), _ptr(XR))
+    return QL, QR, XL, XR
+
+
+def to_bf16(X, ld: int | None = None):
+    """bfloat16 (round to nearest even) copy of X as an int16 tensor whose
+    row pitch is a multiple of 8 elements."""
+    torch = _torch()
+    _need(X, torch.float32, "X", ld_ok=True)
+    n, m = X.shape
+    ldb = ld or ((m + 7) // 8) * 8
+    buf = torch.empty(n, ldb, dtype=torch.int16, device=X.device)
+    _call("cnmf_to_bf16", context().h, n, m, _ptr(X), _ld(X), _ptr(buf), ldb)
+    return buf[:, :m]
+
+
+@dataclass
+class SolveTrace:
+    steps: object
+    lips: object
+    tols: object
+    ticks: object
+    G_hist: object
+    F_hist: object
+
+
+def make_trace(n: int, m: int, p: int, T: int, device, history: bool = True) -> SolveTrace:
+    torch = _torch()
+    return SolveTrace(
+        steps=torch.zeros(T, 2, dtype=torch.int32, device=device),
+        lips=torch.zeros(T, 2, dtype=torch.float64, device=device),
+        tols=torch.zeros(T, 2, dtype=torch.float64, device=device),
+        ticks=torch.zeros(T + 1, dtype=torch.int64, device=device),
+        G_hist=torch.empty(T, n, p, device=device) if history else None,
+        F_hist=torch.empty(T, p, m, device=device) if history else None)
+
+
+def solve(G, F, *, X=None, compressed=None, p: int | None = None, nu: int = 10,
+          outer_iters: int = 200, inner_max: int = 500, inner_min: int = 1,
+          inner_ratio: float = 1e-3, stop_rule: int = STOP_GLOBAL, trace: SolveTrace | None = None,
+          replay=None):
+    """NeNMF outer loop in place on G (n x p) and F (p x m).  Plain when
+    ``compressed`` is None (needs X), else ``compressed = (Q_L, Q_R, X_L, X_R)``
+    from ``rsi``."""
+    torch = _torch()
+    n, pp = G.shape
+    p = pp if p is None else p
+    m = F.shape[1]
+    _need(G, torch.float32, "G", (n, p))
+    _need(F, torch.float32, "F", (p, m))
+    method = METHOD_PLAIN if compressed is None else METHOD_COMPRESSED
+    ell = p
+    QL = QR = XL = XR = None
+    if compressed is not None:
+        QL, QR, XL, XR = compressed
+        ell = QL.shape[1]
+        nu = ell - p
+        _need(QL, torch.float32, "Q_L", (n, ell))
+        _need(QR, torch.float32, "Q_R", (m, ell))
+        _need(XL, torch.float32, "X_L", (ell, m))
+        _need(XR, torch.float32, "X_R", (n, ell))
+    if X is not None:
+        _need(X, torch.float32, "X", (n, m), ld_ok=True)
+    elif method == METHOD_PLAIN:
+        raise ValueError("plain NeNMF needs X")
+    if replay is not None:
+        _need(replay, torch.int32, "replay", (outer_iters, 2))
+    prm = params(p, nu, 1, outer_iters, inner_max, inner_min, inner_ratio, stop_rule=stop_rule)
+    tr = None
+    if trace is not None:
+        tr = Trace(*[ctypes.c_void_p(0 if t is None else t.data_ptr()) for t in
+                     (trace.steps, trace.lips, trace.tols, trace.ticks, trace.G_hist, trace.F_hist)])
+    _call("cnmf_solve", context().h, method, n, m, _ptr(X), _ld(X) if X is not None else m,
+          _ptr(QL), _ptr(QR), _ptr(XL), _ptr(XR), ctypes.byref(prm), _ptr(G), _ptr(F),
+          ctypes.byref(tr) if tr is not None else None, _ptr(replay))
+    return G, F
+
+
+def rre(X, G, F, out=None):
+    """Relative reconstruction error (Eq. (4)); G (n x p) or (count, n, p),
+    F (p x m) or (count, p, m).  Returns a float64 device tensor."""
+    torch = _torch()
+    n, m = X.shape
+    _need(X, torch.float32, "X", ld_ok=True)
+    single = G.dim() == 2
+    G3 = G.unsqueeze(0) if single else G
+    F3 = F.unsqueeze(0) if single else F
+    count, _, p = G3.shape
+    if not (G3.is_contiguous() and F3.is_contiguous()) or F3.shape != (count, p, m):
+        raise ValueError("G, F must be contiguous (count, n, p), (count, p, m)")
+    if out is None:
+        out = torch.empty(count, dtype=torch.float64, device=X.device)
+    _call("cnmf_rre", context().h, n, m, _ptr(X), _ld(X), p, _ptr(G3), n * p, _ptr(F3), p * m,
+          count, _ptr(out))
+    return out[0] if single else out
+
+
+# ---------------------------------------------------------------------------
+# Kernel-level entry points
+# ---------------------------------------------------------------------------
+
+def sweep_right(X, A, a_trans: bool = False, out=None):
+    """Y = X A with A (C x k), or A given as its transpose (k x C)."""
+    torch = _torch()
+    _need(X, torch.float32, "X", ld_ok=True)
+    _need(A, torch.float32, "A", ld_ok=True)
+    R, C = X.shape
+    k = A.shape[0] if a_trans else A.shape[1]
+    if (A.shape[1] if a_trans else A.shape[0]) != C:
+        raise ValueError("inner dimensions differ")
+    Y = torch.empty(R, k, device=X.device) if out is None else out
+    _call("cnmf_sweep_right", context().h, R, C, _ptr(X), _ld(X), k, _ptr(A), _ld(A),
+          1 if a_trans else 0, _ptr(Y), _ld(Y))
+    return Y
+
+
+def sweep_left(X, B, z_trans: bool = False, out=None):
+    """Z = X^T B (C x k), or its transpose (k x C)."""
+    torch = _torch()
+    _need(X, torch.float32, "X", ld_ok=True)
+    _need(B, torch.float32, "B", ld_ok=True)
+    R, C = X.shape
+    k = B.shape[1]
+    if B.shape[0] != R:
+        raise ValueError("inner dimensions differ")
+    Z = (torch.empty(k, C, device=X.device) if z_trans else torch.empty(C, k, device=X.device)) \
+        if out is None else out
+    _call("cnmf_sweep_left", context().h, R, C, _ptr(X), _ld(X), k, _ptr(B), _ld(B), _ptr(Z),
+          _ld(Z), 1 if z_trans else 0)
+    return Z
+
+
+def orth(Y, pool, pool_trans: bool = False, tau2: float = 1e-9):
+    """CholeskyQR2 basis of Y (N x l) with the rank rule; returns (Q, replaced)."""
+    torch = _torch()
+    N, ell = Y.shape
+    _need(Y, torch.float32, "Y", (N, ell))
+    _need(pool, torch.float32, "pool", (ell, N) if pool_trans else (N, ell))
+    Q = torch.empty_like(Y)
+    rep = torch.zeros(ell, dtype=torch.int32, device=Y.device)
+    _call("cnmf_orth", context().h, N, ell, _ptr(Y), _ptr(pool), 1 if pool_trans else 0,
+          tau2, _ptr(Q), _ptr(rep))
+    return Q, rep
+
+
+def lipschitz(W):
+    torch = _torch()
+    p = W.shape[0]
+    _need(W, torch.float32, "W", (p, p))
+    out = torch.empty(1, dtype=torch.float64, device=W.device)
+    _call("cnmf_lipschitz", context().h, p, _ptr(W), _ptr(out))
+    return out
+
+
+def nnls(Z, W, B, tol: float, inner_max: int, inner_min: int = 1, forced: int = -1,
+         by_columns: bool = False):
+    """One Nesterov inner loop in place on Z: rows of Z (G side) or, with
+    by_columns, columns of Z (F side, Z is p x m).  Returns (steps, L, pg0^2)
+    as device tensors."""
+    torch = _torch()
+    p = W.shape[0]
+    _need(W, torch.float32, "W", (p, p))
+    if by_columns:
+        _need(Z, torch.float32, "Z", (p, Z.shape[1]))
+        rows, rs, cs = Z.shape[1], 1, Z.shape[1]
+    else:
+        _need(Z, torch.float32, "Z", (Z.shape[0], p))
+        rows, rs, cs = Z.shape[0], p, 1
+    _need(B, torch.float32, "B", (rows, p))
+    steps = torch.zeros(1, dtype=torch.int32, device=Z.device)
+    L = torch.zeros(1, dtype=torch.float64, device=Z.device)
+    pg2 = torch.zeros(1, dtype=torch.float64, device=Z.device)
+    _call("cnmf_nnls", context().h, rows, p, _ptr(Z), rs, cs, _ptr(W), _ptr(B), tol,
+          inner_max, inner_min, forced, _ptr(steps), _ptr(L), _ptr(pg2))
+    return steps, L, pg2

@@ -1,0 +1,176 @@
+// Internal declarations shared by the HIP translation units of libcnmf.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cnmf.h"
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+namespace cnmf {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Device-side control block, one per context (device memory, zeroed at
+// creation).  Grid barriers of the persistent kernels live here.
+// ---------------------------------------------------------------------------
+struct Control {
+    unsigned bar_count;   // arrivals at the current grid barrier
+    unsigned bar_gen;     // barrier generation, grows forever
+    int status;           // CNMF_ST_* bits
+    int pad0;
+    double pg2[4];        // scratch for initial projected-gradient norms
+    double tol[2];        // running gradient bounds (G, F) of the global rule
+};
+
+// Spin limit of a grid barrier: about a second of polling before the
+// barrier gives up, flags CNMF_ST_TIMEOUT and lets every wave leave.
+constexpr unsigned kSpinLimit = 1u << 24;
+
+__device__ __forceinline__ int atomic_status_load(int* s) {
+    return __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void raise_status(Control* ctl, int bits) {
+    __hip_atomic_fetch_or(&ctl->status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sense-free generation barrier across all workgroups of a grid whose
+// workgroups are all resident (grid size <= number of CUs).  Every thread
+// of every workgroup must call it.  Returns false when the barrier timed
+// out or a timeout was already flagged; callers then leave their loops.
+__device__ __forceinline__ bool grid_sync(Control* ctl, unsigned nblocks) {
+    __shared__ int s_ok;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned g = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned a = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        if (a == nblocks - 1) {
+            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(1);
+                if (((++spins) & 1023u) == 0u) {
+                    if (spins >= kSpinLimit || (atomic_status_load(&ctl->status) & CNMF_ST_TIMEOUT)) {
+                        raise_status(ctl, CNMF_ST_TIMEOUT);
+                        ok = 0;
+                        break;
+                    }
+                }
+            }
+        }
+        if (atomic_status_load(&ctl->status) & CNMF_ST_TIMEOUT) ok = 0;
+        s_ok = ok;
+    }
+    __syncthreads();
+    __threadfence();
+    return s_ok != 0;
+}
+
+// Wavefront sum (64 lanes) in FP64, fixed butterfly order: every lane ends
+// with the same value, bit-identical across runs.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers (defined in the .hip files, called by api.cpp).
+// All return hipSuccess or the launch error.
+// ---------------------------------------------------------------------------
+struct Dev {
+    int device;
+    int num_cus;
+    hipStream_t stream;
+};
+
+// sweep.hip
+size_t sweep_right_partial_floats(const Dev& d, int64_t R, int64_t C);
+hipError_t sweep_right(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx,
+                       int k, const float* A, int64_t lda, bool a_trans, float* Y,
+                       int64_t ldy, float* partial);
+size_t sweep_left_partial_floats(const Dev& d, int64_t R, int64_t C);
+hipError_t sweep_left(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx,
+                      int k, const float* B, int64_t ldb, float* Z, int64_t ldz,
+                      bool z_trans, float* partial);
+size_t sweep_right_bf16_partial_floats(const Dev& d, int64_t R, int64_t C);
+hipError_t sweep_right_bf16(const Dev& d, int64_t R, int64_t C, const uint16_t* Xb,
+                            int64_t ldx, int k, const float* A, int64_t lda, float* Y,
+                            int64_t ldy, float* partial, uint16_t* abuf);
+size_t sweep_left_bf16_partial_floats(const Dev& d, int64_t R, int64_t C);
+hipError_t sweep_left_bf16(const Dev& d, int64_t R, int64_t C, const uint16_t* Xb,
+                           int64_t ldx, int k, const float* B, int64_t ldb, float* Z,
+                           int64_t ldz, bool z_trans, float* partial, uint16_t* bbuf);
+hipError_t to_bf16(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx,
+                   uint16_t* Xb, int64_t ldxb);
+hipError_t transpose(const Dev& d, int64_t R, int64_t C, const float* A, int64_t lda,
+                     float* B, int64_t ldb);
+hipError_t check_input(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx,
+                       Control* ctl);
+
+// orth.hip: workspace in doubles for an N x l panel
+size_t orth_workspace_doubles(const Dev& d, int64_t N, int l);
+hipError_t orth(const Dev& d, int64_t N, int l, const float* Y, const float* pool,
+                bool pool_trans, double tau2, float* Q, int32_t* replaced, double* ws,
+                Control* ctl);
+
+// small.hip
+hipError_t lipschitz(const Dev& d, int p, const float* W, double* out, Control* ctl);
+
+// nesterov.hip
+struct NnlsArgs {
+    int64_t rows;
+    int p;
+    float* Z;
+    int64_t z_rs, z_cs;
+    const float* W;
+    const float* B;
+    const double* L;          // device, from lipschitz()
+    const double* tol_ptr;    // device gradient bound (global rule) or nullptr
+    double tol_value;         // used when tol_ptr == nullptr and ratio == 0
+    double ratio;             // > 0: per-subproblem rule, tol = ratio*||PG(Z0)||
+    double* tol_state;        // device: divided by 10 after an early stop (global rule)
+    int inner_max, inner_min;
+    int forced;               // >= 0 forces that many steps
+    const int32_t* forced_ptr;// device replay entry (overrides forced when set)
+    int32_t* steps_out;       // device, may be null
+    double* L_out;            // device copy of L, may be null
+    double* tol_out;          // device record of the tolerance used, may be null
+    double* pg2_out;          // device ||PG(Z0)||^2, may be null
+    float* hist;              // copy of the result (same layout), may be null
+    unsigned long long* tick_out;  // device clock at exit (atomic max), may be null
+    bool pg_only;             // compute pg2_out only, leave Z
+};
+hipError_t nnls(const Dev& d, const NnlsArgs& a, double* partials, Control* ctl);
+size_t nnls_partial_doubles(const Dev& d, int64_t rows);
+
+// misc kernels (small.hip)
+hipError_t tol_init(const Dev& d, Control* ctl, double ratio);
+hipError_t write_tick(const Dev& d, unsigned long long* tick);
+hipError_t fill_u64(const Dev& d, uint64_t* p, int64_t count, uint64_t value);
+hipError_t rre(const Dev& d, int64_t n, int64_t m, const float* X, int64_t ldx, int p,
+               const float* G, int64_t sG, const float* F, int64_t sF, int count,
+               double* out, double* partial, int64_t partial_len);
+size_t rre_partial_doubles(const Dev& d, int64_t n, int64_t m, int count);
+
+}  // namespace cnmf

@@ -1,0 +1,183 @@
+"""Per-kernel parity of the HIP path (through the C ABI) with the FP64
+oracle and library primitives, on identical seeded FP32 inputs."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev, host, rel_fro, say
+
+pytestmark = pytest.mark.gpu
+
+cnmf = pytest.importorskip("paper_1812_04315_amd")
+
+
+def _bound(X, A):
+    """Elementwise FP32 dot-product error scale |X| |A|."""
+    return np.abs(X) @ np.abs(A)
+
+
+@pytest.mark.parametrize("R,C,k,ld", [
+    (1, 1, 1, None), (31, 33, 5, None), (200, 150, 15, None), (257, 1000, 25, 1003),
+    (1000, 97, 32, 100), (64, 4096, 16, 4096), (3, 2000, 7, None), (513, 777, 30, 780)])
+@pytest.mark.parametrize("a_trans", [False, True])
+def test_sweep_right(R, C, k, ld, a_trans):
+    say("sweep_right", R, C, k, ld, a_trans)
+    rng = np.random.default_rng(R * 7 + C + k)
+    X = rng.random((R, C)).astype(np.float32)
+    A = rng.standard_normal((C, k)).astype(np.float32)
+    Xd = dev(X, ld)
+    Ad = dev(A.T.copy()) if a_trans else dev(A)
+    Y = host(cnmf.sweep_right(Xd, Ad, a_trans=a_trans))
+    ref = X.astype(np.float64) @ A.astype(np.float64)
+    assert np.all(np.abs(Y - ref) <= 1e-5 * _bound(X, A) + 1e-30)
+
+
+@pytest.mark.parametrize("R,C,k,ld", [
+    (1, 1, 1, None), (33, 31, 5, None), (200, 150, 15, None), (1000, 257, 25, 260),
+    (97, 1000, 32, 1001), (4096, 64, 16, None), (2000, 3, 7, None), (777, 513, 30, 516)])
+@pytest.mark.parametrize("z_trans", [False, True])
+def test_sweep_left(R, C, k, ld, z_trans):
+    say("sweep_left", R, C, k, ld, z_trans)
+    rng = np.random.default_rng(R * 5 + C + k)
+    X = rng.random((R, C)).astype(np.float32)
+    B = rng.standard_normal((R, k)).astype(np.float32)
+    Z = host(cnmf.sweep_left(dev(X, ld), dev(B), z_trans=z_trans))
+    if z_trans:
+        Z = Z.T
+    ref = X.T.astype(np.float64) @ B.astype(np.float64)
+    assert np.all(np.abs(Z - ref) <= 1e-5 * _bound(X.T, B) + 1e-30)
+
+
+def test_sweep_bitwise_repeatable():
+    rng = np.random.default_rng(0)
+    X = dev(rng.random((3000, 2000)))
+    A = dev(rng.standard_normal((2000, 25)))
+    a = host(cnmf.sweep_right(X, A))
+    b = host(cnmf.sweep_right(X, A))
+    assert np.array_equal(a, b)
+    c = host(cnmf.sweep_left(X, dev(rng.standard_normal((3000, 25)))))
+    d = host(cnmf.sweep_left(X, dev(rng.standard_normal((3000, 25)))))
+    assert not np.array_equal(c, d)   # different inputs, sanity
+    B = dev(rng.standard_normal((3000, 25)))
+    assert np.array_equal(host(cnmf.sweep_left(X, B)), host(cnmf.sweep_left(X, B)))
+
+
+@pytest.mark.parametrize("N,ell", [(40, 1), (200, 15), (1000, 25), (3001, 32), (32, 32)])
+def test_orth_full_rank(N, ell):
+    say("orth_full_rank", N, ell)
+    rng = np.random.default_rng(N + ell)
+    Y = (rng.standard_normal((N, ell)) @ np.diag(np.geomspace(1, 1e-3, ell))).astype(np.float32)
+    P = rng.standard_normal((N, ell)).astype(np.float32)
+    Q, rep = cnmf.orth(dev(Y), dev(P))
+    Qh = host(Q)
+    Qo, repo = oracle.orth(Y, P)
+    assert host(rep).astype(bool).tolist() == repo.tolist()
+    assert rel_fro(Qh, Qo) <= 1e-4
+    assert np.linalg.norm(Qh.T @ Qh - np.eye(ell)) <= 1e-5
+
+
+@pytest.mark.parametrize("pool_trans", [False, True])
+def test_orth_rank_deficient(pool_trans):
+    say("orth_rank_deficient", pool_trans)
+    rng = np.random.default_rng(3)
+    N, ell, r = 300, 12, 5
+    Y = (rng.random((N, r)) @ rng.random((r, ell))).astype(np.float32)
+    Y[:, 7] = 0.0
+    P = rng.standard_normal((N, ell)).astype(np.float32)
+    Q, rep = cnmf.orth(dev(Y), dev(P.T.copy()) if pool_trans else dev(P), pool_trans=pool_trans)
+    Qo, repo = oracle.orth(Y, P)
+    assert host(rep).astype(bool).tolist() == repo.tolist()
+    assert repo.sum() == ell - r
+    assert rel_fro(host(Q), Qo) <= 1e-4
+
+
+def test_orth_breakdown_flag():
+    say("orth_breakdown")
+    rng = np.random.default_rng(4)
+    Y = rng.standard_normal((100, 4)).astype(np.float32)
+    Y[:, 3] = Y[:, 0]
+    P = rng.standard_normal((100, 4)).astype(np.float32)
+    P[:, 3] = Y[:, 1]
+    cnmf.orth(dev(Y), dev(P))
+    with pytest.raises(cnmf.CnmfError) as ei:
+        cnmf.check()
+    assert ei.value.status & cnmf.ST_BREAKDOWN
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 15, 20, 31, 32])
+def test_lipschitz(p):
+    say("lipschitz", p)
+    rng = np.random.default_rng(p)
+    M = rng.random((p, 3 * p + 5)).astype(np.float32)
+    W = (M.astype(np.float64) @ M.T).astype(np.float32)
+    L = float(host(cnmf.lipschitz(dev(W)))[0])
+    Lo = oracle.lipschitz(W)
+    assert abs(L - Lo) <= 1e-12 * Lo
+    Wz = np.zeros((p, p), np.float32)
+    assert float(host(cnmf.lipschitz(dev(Wz)))[0]) == 0.0
+
+
+@pytest.mark.parametrize("rows,p", [(1, 1), (200, 5), (1000, 15), (5000, 20), (257, 32)])
+@pytest.mark.parametrize("forced", [1, 2, 7, 60])
+def test_nnls_forced_rows(rows, p, forced):
+    say("nnls_forced_rows", rows, p, forced)
+    rng = np.random.default_rng(rows + p + forced)
+    A = rng.random((3 * p + 2, p))
+    W = (A.T @ A).astype(np.float32)
+    B = (rng.random((rows, 3 * p + 2)) @ A).astype(np.float32)
+    Z0 = rng.random((rows, p)).astype(np.float32)
+    Z = dev(Z0)
+    steps, L, _ = cnmf.nnls(Z, dev(W), dev(B), 0.0, 1000, forced=forced)
+    Zo, ko, Lo = oracle.nesterov_nnls(Z0, W, B, "G", 0.0, 1000, forced_steps=forced)
+    assert int(host(steps)[0]) == forced == ko
+    assert abs(float(host(L)[0]) - Lo) <= 1e-12 * Lo
+    assert rel_fro(host(Z), Zo) <= 1e-5
+
+
+@pytest.mark.parametrize("m,p", [(150, 5), (3000, 15), (777, 25)])
+def test_nnls_forced_columns(m, p):
+    say("nnls_forced_columns", m, p)
+    rng = np.random.default_rng(m + p)
+    A = rng.random((2 * p + 1, p))
+    W = (A.T @ A).astype(np.float32)
+    Bt = (rng.random((m, 2 * p + 1)) @ A).astype(np.float32)   # m x p = B^T
+    F0 = rng.random((p, m)).astype(np.float32)
+    F = dev(F0)
+    cnmf.nnls(F, dev(W), dev(Bt), 0.0, 100, forced=9, by_columns=True)
+    Fo, _, _ = oracle.nesterov_nnls(F0, W, Bt.T, "F", 0.0, 100, forced_steps=9)
+    assert rel_fro(host(F), Fo) <= 1e-5
+
+
+@pytest.mark.parametrize("rows,p,tol", [(500, 5, 1e-2), (3000, 15, 1e-3), (9000, 20, 1e-1)])
+def test_nnls_stopping_rule(rows, p, tol):
+    """Tolerance-driven stop: same count as the oracle unless the oracle's
+    margin at the decisive step is below FP32 resolution."""
+    say("nnls_stop", rows, p, tol)
+    rng = np.random.default_rng(rows)
+    A = rng.random((3 * p, p))
+    W = (A.T @ A).astype(np.float32)
+    B = (rng.random((rows, 3 * p)) @ A).astype(np.float32)
+    Z0 = rng.random((rows, p)).astype(np.float32)
+    pg0 = oracle.pg_norm(Z0.astype(float), W.astype(float), B.astype(float), "G")
+    t = tol * pg0
+    Z = dev(Z0)
+    steps, _, pg2 = cnmf.nnls(Z, dev(W), dev(B), t, 5000)
+    Zo, ko, _ = oracle.nesterov_nnls(Z0, W, B, "G", t, 5000)
+    assert abs(np.sqrt(float(host(pg2)[0])) - pg0) <= 1e-5 * pg0
+    k = int(host(steps)[0])
+    assert abs(k - ko) <= 1
+    if k == ko:
+        assert rel_fro(host(Z), Zo) <= 1e-4
+
+
+def test_rre_matches_oracle():
+    say("rre")
+    rng = np.random.default_rng(9)
+    n, m, p = 333, 517, 7
+    X = rng.random((n, m)).astype(np.float32)
+    Gs = rng.random((3, n, p)).astype(np.float32)
+    Fs = rng.random((3, p, m)).astype(np.float32)
+    out = host(cnmf.rre(dev(X, 520), dev(Gs.reshape(3 * n, p)).view(3, n, p),
+                        dev(Fs.reshape(3 * p, m)).view(3, p, m)))
+    for i in range(3):
+        assert abs(out[i] - oracle.rre(X, Gs[i], Fs[i])) <= 1e-10 * out[i]
