@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -15,6 +16,9 @@ using namespace cnmf;
 struct cnmf_ctx {
     Dev dev;
     Control* ctl = nullptr;       // device
+    uint64_t* slots = nullptr;    // device, tagged exchange words of the phase kernels
+    unsigned seq = 0;             // last tag used
+    int dlag = 2;                 // steps between a norm and its stopping test
     char* ws = nullptr;           // device workspace
     size_t ws_bytes = 0;
     double clock_hz = 1e8;
@@ -23,6 +27,18 @@ struct cnmf_ctx {
 namespace {
 
 int from_hip(hipError_t e) { return e == hipSuccess ? CNMF_OK : CNMF_EHIP; }
+
+// Tag of the next phase launch; tags are 22 bits, so the words are cleared
+// whenever the sequence wraps and no stale word can ever match.
+hipError_t next_seq(cnmf_ctx* c, unsigned* seq) {
+    if (++c->seq >= (1u << 22)) {
+        hipError_t e = fill_u64(c->dev, c->slots, (int64_t)kSlotWords, 0);
+        if (e != hipSuccess) return e;
+        c->seq = 1;
+    }
+    *seq = c->seq;
+    return hipSuccess;
+}
 
 #define CK(x)                                   \
     do {                                        \
@@ -139,10 +155,22 @@ int cnmf_create(cnmf_ctx** out, int device, void* stream) {
         delete c;
         return CNMF_ENOMEM;
     }
-    if (hipMemset(c->ctl, 0, sizeof(Control)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    if (hipMalloc((void**)&c->slots, kSlotWords * sizeof(uint64_t)) != hipSuccess) {
         (void)hipFree(c->ctl);
         delete c;
+        return CNMF_ENOMEM;
+    }
+    if (hipMemset(c->ctl, 0, sizeof(Control)) != hipSuccess ||
+        hipMemset(c->slots, 0, kSlotWords * sizeof(uint64_t)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(c->ctl);
+        (void)hipFree(c->slots);
+        delete c;
         return CNMF_EHIP;
+    }
+    if (const char* e = std::getenv("CNMF_DLAG")) {
+        const int v = std::atoi(e);
+        if (v >= 0 && v <= 4) c->dlag = v;
     }
     *out = c;
     return CNMF_OK;
@@ -154,6 +182,7 @@ int cnmf_destroy(cnmf_ctx* c) {
     (void)hipStreamSynchronize(c->dev.stream);
     if (c->ws) (void)hipFree(c->ws);
     if (c->ctl) (void)hipFree(c->ctl);
+    if (c->slots) (void)hipFree(c->slots);
     delete c;
     return CNMF_OK;
 }
@@ -260,32 +289,32 @@ int cnmf_nnls(cnmf_ctx* c, int64_t rows, int32_t p, float* Z, int64_t z_rs, int6
     if (!c || rows < 1 || p < 1 || p > 32) return CNMF_EINVAL;
     if (bad_ptr(Z) || bad_ptr(W) || bad_ptr(B)) return CNMF_EINVAL;
     if (inner_max < 1 || inner_max > 100000 || inner_min < 1) return CNMF_EINVAL;
-    if ((rows + 255) / 256 > c->dev.num_cus) return CNMF_EINVAL;
-    Arena a;
-    size_t offL = a.take<double>(1);
-    size_t offP = a.take<double>(nnls_partial_doubles(c->dev, rows));
-    int rc = ensure_ws(c, a.off);
-    if (rc) return rc;
+    int tiles = 0;
+    unsigned nblk = 0;
+    if (!phase_grid(c->dev, rows, &tiles, &nblk)) return CNMF_EINVAL;
     if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
-    double* Ld = at<double>(c, offL);
-    CK(lipschitz(c->dev, p, W, Ld, c->ctl));
-    NnlsArgs na{};
-    na.rows = rows;
-    na.p = p;
-    na.Z = Z;
-    na.z_rs = z_rs;
-    na.z_cs = z_cs;
-    na.W = W;
-    na.B = B;
-    na.L = Ld;
-    na.tol_value = tol;
-    na.inner_max = inner_max;
-    na.inner_min = inner_min;
-    na.forced = forced;
-    na.steps_out = steps_out;
-    na.L_out = L_out;
-    na.pg2_out = pg2_out;
-    return from_hip(nnls(c->dev, na, at<double>(c, offP), c->ctl));
+    PhaseArgs a{};
+    a.rows = rows;
+    a.p = p;
+    a.mode = 0;
+    a.Z = Z;
+    a.z_rs = z_rs;
+    a.z_cs = z_cs;
+    a.Wgiven = W;
+    a.Bgiven = B;
+    a.slot_s = c->slots;
+    a.slot_pg = c->slots + 1024;
+    a.ctl = c->ctl;
+    a.tol_value = tol;
+    a.inner_max = inner_max;
+    a.inner_min = inner_min;
+    a.forced = forced;
+    a.dlag = c->dlag;
+    a.steps_out = steps_out;
+    a.L_out = L_out;
+    a.pg2_out = pg2_out;
+    CK(next_seq(c, &a.seq));
+    return from_hip(phase(c->dev, a, nblk, tiles));
 }
 
 // ---------------------------------------------------------------------------
@@ -415,122 +444,133 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
     } else if (bad_ptr(X) || ldx < m) {
         return CNMF_EINVAL;
     }
-    if ((n + 255) / 256 > c->dev.num_cus || (m + 255) / 256 > c->dev.num_cus) return CNMF_EINVAL;
+    int tilesG = 0, tilesF = 0;
+    unsigned nbG = 0, nbF = 0;
+    if (!phase_grid(c->dev, n, &tilesG, &nbG) || !phase_grid(c->dev, m, &tilesF, &nbF))
+        return CNMF_EINVAL;
     const int p = prm->p;
     const int l = comp ? p + prm->nu : 0;
     const int T = prm->outer_iters;
     cnmf_trace tr{};
     if (trace) tr = *trace;
 
-    Arena a;
-    const size_t o_W = a.take<float>(32 * 32);
-    const size_t o_BG = a.take<float>((size_t)n * p);
-    const size_t o_BF = a.take<float>((size_t)m * p);
-    const size_t o_FR = a.take<float>(32 * 32);
-    const size_t o_GL = a.take<float>(32 * 32);
-    const size_t o_L = a.take<double>(2);
-    size_t part = std::max(sweep_right_partial_floats(c->dev, n, comp ? l : m),
-                           sweep_left_partial_floats(c->dev, comp ? l : n, m));
-    part = std::max(part, sweep_right_partial_floats(c->dev, p, m));       // F Q_R, F F^T
-    part = std::max(part, sweep_left_partial_floats(c->dev, n, std::max(l, p)));  // Q_L^T G, G^T G
-    part = std::max(part, sweep_right_partial_floats(c->dev, 32, 32));
-    part = std::max(part, sweep_left_partial_floats(c->dev, 32, 32));
-    const size_t o_part = a.take<float>(part);
-    const size_t o_np = a.take<double>(nnls_partial_doubles(c->dev, std::max(n, m)));
-    rc = ensure_ws(c, a.off);
+    Arena ar;
+    const size_t o_pG = ar.take<float>((size_t)nbG * 1024);
+    const size_t o_pF = ar.take<float>((size_t)nbF * 1024);
+    const size_t o_BG = ar.take<float>(comp ? 1 : (size_t)n * p);
+    const size_t o_BF = ar.take<float>(comp ? 1 : (size_t)m * p);
+    const size_t o_sw = ar.take<float>(comp ? 1 : std::max(sweep_right_partial_floats(c->dev, n, m),
+                                                            sweep_left_partial_floats(c->dev, n, m)));
+    rc = ensure_ws(c, ar.off);
     if (rc) return rc;
     if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
     const Dev& d = c->dev;
-    float* W = at<float>(c, o_W);
+    float* pG = at<float>(c, o_pG);
+    float* pF = at<float>(c, o_pF);
     float* BG = at<float>(c, o_BG);
     float* BF = at<float>(c, o_BF);
-    float* FR = at<float>(c, o_FR);
-    float* GL = at<float>(c, o_GL);
-    double* Ld = at<double>(c, o_L);
-    float* pt = at<float>(c, o_part);
-    double* np = at<double>(c, o_np);
+    float* sw = at<float>(c, o_sw);
     Control* ctl = c->ctl;
-
-    // Subproblem data of Eq. (2) for the current F: W = F F^T, B = X F^T, or
-    // Algorithm 1's F_R = F R, W = F_R F_R^T, B = X_R F_R^T.
-    auto gdata = [&]() -> hipError_t {
-        hipError_t e;
-        if (comp) {
-            if ((e = sweep_right(d, p, m, F, m, l, Q_R, l, false, FR, l, pt))) return e;
-            if ((e = sweep_right(d, p, l, FR, l, p, FR, l, true, W, p, pt))) return e;
-            return sweep_right(d, n, l, X_R, l, p, FR, l, true, BG, p, pt);
-        }
-        if ((e = sweep_right(d, p, m, F, m, p, F, m, true, W, p, pt))) return e;
-        return sweep_right(d, n, m, X, ldx, p, F, m, true, BG, p, pt);
-    };
-    // Eq. (3) for the current G: W = G^T G, B^T = X^T G, or Algorithm 1's
-    // G_L = L G, W = G_L^T G_L, B^T = X_L^T G_L.
-    auto fdata = [&]() -> hipError_t {
-        hipError_t e;
-        if (comp) {
-            if ((e = sweep_left(d, n, l, Q_L, l, p, G, p, GL, p, false, pt))) return e;
-            if ((e = sweep_left(d, l, p, GL, p, p, GL, p, W, p, false, pt))) return e;
-            return sweep_left(d, l, m, X_L, m, p, GL, p, BF, p, false, pt);
-        }
-        if ((e = sweep_left(d, n, p, G, p, p, G, p, W, p, false, pt))) return e;
-        return sweep_left(d, n, m, X, ldx, p, G, p, BF, p, false, pt);
-    };
-    auto gargs = [&]() {
-        NnlsArgs na{};
-        na.rows = n; na.p = p; na.Z = G; na.z_rs = p; na.z_cs = 1; na.W = W; na.B = BG;
-        na.L = Ld; na.inner_max = prm->inner_max; na.inner_min = prm->inner_min; na.forced = -1;
-        return na;
-    };
-    auto fargs = [&]() {
-        NnlsArgs na{};
-        na.rows = m; na.p = p; na.Z = F; na.z_rs = 1; na.z_cs = m; na.W = W; na.B = BF;
-        na.L = Ld; na.inner_max = prm->inner_max; na.inner_min = prm->inner_min; na.forced = -1;
-        return na;
-    };
     const bool global = prm->stop_rule == CNMF_STOP_GLOBAL;
 
+    PhaseArgs base{};
+    base.p = p;
+    base.ell = l;
+    base.mode = comp ? 2 : 1;
+    base.slot_s = c->slots;
+    base.slot_pg = c->slots + 1024;
+    base.ctl = ctl;
+    base.inner_max = prm->inner_max;
+    base.inner_min = prm->inner_min;
+    base.forced = -1;
+    base.dlag = c->dlag;
+    // G update (Eq. (2) / Algorithm 1 with X_R, F_R): rows of G
+    PhaseArgs ga = base;
+    ga.rows = n;
+    ga.Z = G;
+    ga.z_rs = p;
+    ga.z_cs = 1;
+    ga.wt = 0;
+    ga.D = X_R;
+    ga.d_rs = l;
+    ga.d_cs = 1;
+    ga.Q = Q_L;
+    ga.Bgiven = BG;
+    ga.part_in = pF;
+    ga.nin = (int)nbF;
+    ga.part_out = pG;
+    // F update (Eq. (3) / Algorithm 1 with X_L, G_L): columns of F
+    PhaseArgs fa = base;
+    fa.rows = m;
+    fa.Z = F;
+    fa.z_rs = 1;
+    fa.z_cs = m;
+    fa.wt = 1;
+    fa.D = X_L;
+    fa.d_rs = 1;
+    fa.d_cs = m;
+    fa.Q = Q_R;
+    fa.Bgiven = BF;
+    fa.part_in = pG;
+    fa.nin = (int)nbG;
+    fa.part_out = pF;
+
+    auto run = [&](PhaseArgs a, bool is_g) -> hipError_t {
+        hipError_t e = next_seq(c, &a.seq);
+        if (e != hipSuccess) return e;
+        return phase(d, a, is_g ? nbG : nbF, is_g ? tilesG : tilesF);
+    };
+    auto bg = [&]() -> hipError_t {   // plain: B_G = X F^T
+        return comp ? hipSuccess : sweep_right(d, n, m, X, ldx, p, F, m, true, BG, p, sw);
+    };
+    auto bf = [&]() -> hipError_t {   // plain: B_F^T = X^T G
+        return comp ? hipSuccess : sweep_left(d, n, m, X, ldx, p, G, p, BF, p, false, sw);
+    };
+
     if (tr.ticks) CK(write_tick(d, (unsigned long long*)tr.ticks));
+    {   // partial product of F0 for the first G update
+        PhaseArgs a = fa;
+        a.kind = 2;
+        CK(run(a, false));
+    }
     if (T > 0 && global) {
-        // Gradient bound: ratio * ||(P grad_G, P grad_F)|| at (G0, F0).
-        CK(gdata());
-        NnlsArgs na = gargs();
-        na.pg_only = true;
-        na.pg2_out = &ctl->pg2[0];
-        CK(nnls(d, na, np, ctl));
-        CK(fdata());
-        na = fargs();
-        na.pg_only = true;
-        na.pg2_out = &ctl->pg2[1];
-        CK(nnls(d, na, np, ctl));
-        CK(tol_init(d, ctl, prm->inner_ratio));
+        // gradient bound: ratio * ||(P grad_G, P grad_F)|| at (G0, F0)
+        CK(bg());
+        PhaseArgs a = ga;
+        a.kind = 1;
+        a.pg2_out = &ctl->pg2[0];
+        CK(run(a, true));
+        CK(bf());
+        a = fa;
+        a.kind = 1;
+        a.pg2_out = &ctl->pg2[1];
+        a.tol_init_from = &ctl->pg2[0];
+        a.ratio = prm->inner_ratio;
+        CK(run(a, false));
     }
     if (tr.ticks && T > 0) CK(fill_u64(d, tr.ticks + 1, T, 0));
     for (int t = 0; t < T; ++t) {
-        CK(gdata());
-        CK(lipschitz(d, p, W, Ld, ctl));
-        NnlsArgs na = gargs();
-        if (global) { na.tol_ptr = &ctl->tol[0]; na.tol_state = &ctl->tol[0]; }
-        else na.ratio = prm->inner_ratio;
-        if (replay) na.forced_ptr = replay + 2 * t;
-        if (tr.steps) na.steps_out = tr.steps + 2 * t;
-        if (tr.lips) na.L_out = tr.lips + 2 * t;
-        if (tr.tols) na.tol_out = tr.tols + 2 * t;
-        if (tr.G_hist) na.hist = tr.G_hist + (size_t)t * n * p;
-        CK(nnls(d, na, np, ctl));
-
-        CK(fdata());
-        CK(lipschitz(d, p, W, Ld + 1, ctl));
-        na = fargs();
-        na.L = Ld + 1;
-        if (global) { na.tol_ptr = &ctl->tol[1]; na.tol_state = &ctl->tol[1]; }
-        else na.ratio = prm->inner_ratio;
-        if (replay) na.forced_ptr = replay + 2 * t + 1;
-        if (tr.steps) na.steps_out = tr.steps + 2 * t + 1;
-        if (tr.lips) na.L_out = tr.lips + 2 * t + 1;
-        if (tr.tols) na.tol_out = tr.tols + 2 * t + 1;
-        if (tr.F_hist) na.hist = tr.F_hist + (size_t)t * p * m;
-        if (tr.ticks) na.tick_out = (unsigned long long*)(tr.ticks + 1 + t);
-        CK(nnls(d, na, np, ctl));
+        CK(bg());
+        PhaseArgs a = ga;
+        if (global) { a.tol_ptr = &ctl->tol[0]; a.tol_state = &ctl->tol[0]; }
+        else a.ratio = prm->inner_ratio;
+        if (replay) a.forced_ptr = replay + 2 * t;
+        if (tr.steps) a.steps_out = tr.steps + 2 * t;
+        if (tr.lips) a.L_out = tr.lips + 2 * t;
+        if (tr.tols) a.tol_out = tr.tols + 2 * t;
+        if (tr.G_hist) a.hist = tr.G_hist + (size_t)t * n * p;
+        CK(run(a, true));
+        CK(bf());
+        a = fa;
+        if (global) { a.tol_ptr = &ctl->tol[1]; a.tol_state = &ctl->tol[1]; }
+        else a.ratio = prm->inner_ratio;
+        if (replay) a.forced_ptr = replay + 2 * t + 1;
+        if (tr.steps) a.steps_out = tr.steps + 2 * t + 1;
+        if (tr.lips) a.L_out = tr.lips + 2 * t + 1;
+        if (tr.tols) a.tol_out = tr.tols + 2 * t + 1;
+        if (tr.F_hist) a.hist = tr.F_hist + (size_t)t * p * m;
+        if (tr.ticks) a.tick_out = (unsigned long long*)(tr.ticks + 1 + t);
+        CK(run(a, false));
     }
     return CNMF_OK;
 }

@@ -137,35 +137,53 @@ hipError_t orth(const Dev& d, int64_t N, int l, const float* Y, const float* poo
 // small.hip
 hipError_t lipschitz(const Dev& d, int p, const float* W, double* out, Control* ctl);
 
-// nesterov.hip
-struct NnlsArgs {
+// solver.hip
+// Kernel arguments of one phase.
+struct PhaseArgs {
     int64_t rows;
     int p;
+    int ell;                 // compressed: l; plain / given: 0
+    int mode;                // 0 given W/B, 1 plain (W from partials, B given), 2 compressed
+    int wt;                  // 1: gradient Z W^T (F update in row form)
     float* Z;
     int64_t z_rs, z_cs;
-    const float* W;
-    const float* B;
-    const double* L;          // device, from lipschitz()
-    const double* tol_ptr;    // device gradient bound (global rule) or nullptr
-    double tol_value;         // used when tol_ptr == nullptr and ratio == 0
-    double ratio;             // > 0: per-subproblem rule, tol = ratio*||PG(Z0)||
-    double* tol_state;        // device: divided by 10 after an early stop (global rule)
-    int inner_max, inner_min;
-    int forced;               // >= 0 forces that many steps
-    const int32_t* forced_ptr;// device replay entry (overrides forced when set)
-    int32_t* steps_out;       // device, may be null
-    double* L_out;            // device copy of L, may be null
-    double* tol_out;          // device record of the tolerance used, may be null
-    double* pg2_out;          // device ||PG(Z0)||^2, may be null
-    float* hist;              // copy of the result (same layout), may be null
-    unsigned long long* tick_out;  // device clock at exit (atomic max), may be null
-    bool pg_only;             // compute pg2_out only, leave Z
+    const float* Bgiven;     // rows x p (modes 0, 1)
+    const float* Wgiven;     // p x p (mode 0)
+    const float* D;          // compressed data, element (r, k) at D[r*d_rs + k*d_cs]
+    int64_t d_rs, d_cs;
+    const float* Q;          // rows x l, row-major (mode 2 epilogue)
+    const float* part_in;    // [nin][32][32] partial products of the previous phase
+    int nin;
+    float* part_out;         // [nblk][32][32] (may be null)
+    uint64_t* slot_s;        // [1024] S exchange
+    uint64_t* slot_pg;       // [kMaxSlot][256][2] projected-gradient exchange
+    unsigned seq;            // launch sequence (tag), 1 .. 2^22 - 1
+    Control* ctl;
+    // stopping
+    const double* tol_ptr;   // global rule: running bound (read)
+    double* tol_state;       // global rule: divided by 10 after an early stop
+    double tol_value;        // given bound (mode 0 without tol_ptr)
+    double ratio;            // > 0: per-subproblem rule
+    int inner_max, inner_min, forced;
+    const int32_t* forced_ptr;
+    int dlag;
+    // outputs
+    int32_t* steps_out;
+    double* L_out;
+    double* tol_out;
+    double* pg2_out;         // ||P grad(Z_0)||^2
+    int kind;                // 0 solve, 1 projected-gradient norm only, 2 partial product only
+    double* tol_init_from;   // with kind 1: tol = ratio*sqrt(pg2 + *tol_init_from) -> ctl->tol
+    float* hist;
+    unsigned long long* tick_out;
 };
-hipError_t nnls(const Dev& d, const NnlsArgs& a, double* partials, Control* ctl);
-size_t nnls_partial_doubles(const Dev& d, int64_t rows);
+
+bool phase_grid(const Dev& d, int64_t rows, int* tiles, unsigned* nblk);
+hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles);
+constexpr int kPgSlots = 10;   // slots per workgroup for projected-gradient partials
+constexpr size_t kSlotWords = 1024 + (size_t)kPgSlots * 256 * 2;
 
 // misc kernels (small.hip)
-hipError_t tol_init(const Dev& d, Control* ctl, double ratio);
 hipError_t write_tick(const Dev& d, unsigned long long* tick);
 hipError_t fill_u64(const Dev& d, uint64_t* p, int64_t count, uint64_t value);
 hipError_t rre(const Dev& d, int64_t n, int64_t m, const float* X, int64_t ldx, int p,

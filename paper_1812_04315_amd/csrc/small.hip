@@ -1,119 +1,10 @@
-// Small-matrix and measurement kernels:
-//   * Lipschitz constant of the inner loop's gradient map (Sec. 2: a single
-//     gradient step per inner iteration; step 1/L with L = lambda_max(W)),
-//     in FP64 by Householder tridiagonalisation and Sturm bisection;
-//   * gradient-bound initialisation and device clock stamps;
-//   * relative reconstruction error (Sec. 4, Eq. (4)).
+// Measurement and bookkeeping kernels: device clock stamps, fills, and the
+// relative reconstruction error of Sec. 4, Eq. (4).
 #include "internal.hpp"
 
 namespace cnmf {
 
 namespace {
-
-// One wavefront.  A = (W + W^T) / 2 in FP64, reduced to tridiagonal form by
-// Householder reflections H = I - 2 v v^T (lane i owns row i); the largest
-// eigenvalue of the tridiagonal matrix is then bracketed between max_i d_i
-// and its Gershgorin bound and narrowed by 64-way Sturm multisection.
-__global__ __launch_bounds__(64) void k_lipschitz(int p, const float* __restrict__ W,
-                                                  double* __restrict__ out, Control* ctl) {
-    __shared__ double A[32][33];
-    __shared__ double v[32], wv[32];
-    __shared__ double dg[32], eo[32];
-    const int lane = threadIdx.x;
-    for (int e = lane; e < p * p; e += 64) {
-        const int i = e / p, j = e % p;
-        A[i][j] = 0.5 * ((double)W[i * p + j] + (double)W[j * p + i]);
-    }
-    __syncthreads();
-    for (int k = 0; k + 2 < p; ++k) {
-        const int i = lane;
-        const bool in = (i > k) && (i < p);
-        const double xi = in ? A[i][k] : 0.0;
-        const double sigma = wave_sum(xi * xi);
-        const double x0 = A[k + 1][k];
-        if (sigma == 0.0) {
-            if (lane == 0) { dg[k] = A[k][k]; eo[k] = 0.0; }
-            __syncthreads();
-            continue;
-        }
-        const double alpha = -copysign(sqrt(sigma), x0);
-        const double v0 = x0 - alpha;
-        const double vn = sqrt(sigma - x0 * x0 + v0 * v0);
-        if (in) v[i] = ((i == k + 1) ? v0 : xi) / vn;
-        __syncthreads();
-        double ui = 0.0;
-        if (in)
-            for (int j = k + 1; j < p; ++j) ui = fma(A[i][j], v[j], ui);
-        const double c = wave_sum(in ? v[i] * ui : 0.0);
-        if (in) wv[i] = 2.0 * ui - 2.0 * c * v[i];
-        __syncthreads();
-        if (in)
-            for (int j = k + 1; j < p; ++j) A[i][j] -= v[i] * wv[j] + wv[i] * v[j];
-        if (lane == 0) { dg[k] = A[k][k]; eo[k] = alpha; }
-        __syncthreads();
-    }
-    if (lane == 0) {
-        if (p >= 2) {
-            dg[p - 2] = A[p - 2][p - 2];
-            eo[p - 2] = A[p - 1][p - 2];
-        }
-        dg[p - 1] = A[p - 1][p - 1];
-    }
-    __syncthreads();
-    // Bracket [lo, hi] around lambda_max.
-    double lo = -INFINITY, hi = -INFINITY, emax = 0.0;
-    bool bad = false;
-    for (int i = 0; i < p; ++i) {
-        const double el = (i > 0) ? fabs(eo[i - 1]) : 0.0;
-        const double er = (i + 1 < p) ? fabs(eo[i]) : 0.0;
-        lo = fmax(lo, dg[i]);
-        hi = fmax(hi, dg[i] + el + er);
-        emax = fmax(emax, er);
-        if (!isfinite(dg[i]) || !isfinite(er)) bad = true;
-    }
-    if (bad) {
-        if (lane == 0) { out[0] = NAN; raise_status(ctl, CNMF_ST_NONFINITE); }
-        return;
-    }
-    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax * emax);
-    for (int round = 0; round < 16 && hi > lo; ++round) {
-        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-        // Sturm count: eigenvalues below x
-        int cnt = 0;
-        double q = dg[0] - x;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0;
-        for (int i = 1; i < p; ++i) {
-            q = (dg[i] - x) - eo[i - 1] * eo[i - 1] / q;
-            if (fabs(q) < pivmin) q = -pivmin;
-            cnt += q < 0.0;
-        }
-        const bool above = (cnt == p);   // lambda_max < x
-        const unsigned long long mask = __ballot(above);
-        double nlo = lo, nhi = hi;
-        if (mask) {
-            const int first = __ffsll((long long)mask) - 1;
-            nhi = __shfl(x, first, 64);
-            if (first > 0) nlo = __shfl(x, first - 1, 64);
-        } else {
-            nlo = __shfl(x, 63, 64);
-        }
-        if (!(nhi - nlo < hi - lo)) break;
-        lo = nlo;
-        hi = nhi;
-        if (hi - lo <= 4.0 * 2.220446049250313e-16 * fabs(hi)) break;
-    }
-    if (lane == 0) out[0] = hi;
-}
-
-__global__ void k_tol_init(Control* ctl, double ratio) {
-    if (threadIdx.x == 0) {
-        const double t = ratio * sqrt(ctl->pg2[0] + ctl->pg2[1]);
-        ctl->tol[0] = t;
-        ctl->tol[1] = t;
-        if (!isfinite(t)) raise_status(ctl, CNMF_ST_NONFINITE);
-    }
-}
 
 __global__ void k_fill_u64(uint64_t* p, int64_t count, uint64_t value) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -189,16 +80,6 @@ int64_t rre_blocks(const Dev& d, int64_t n) {
 }
 
 }  // namespace
-
-hipError_t lipschitz(const Dev& d, int p, const float* W, double* out, Control* ctl) {
-    hipLaunchKernelGGL(k_lipschitz, dim3(1), dim3(64), 0, d.stream, p, W, out, ctl);
-    return hipGetLastError();
-}
-
-hipError_t tol_init(const Dev& d, Control* ctl, double ratio) {
-    hipLaunchKernelGGL(k_tol_init, dim3(1), dim3(64), 0, d.stream, ctl, ratio);
-    return hipGetLastError();
-}
 
 hipError_t write_tick(const Dev& d, unsigned long long* tick) {
     hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, d.stream, tick);

@@ -1,0 +1,670 @@
+// One half of a NeNMF outer iteration as one persistent kernel ("phase").
+//
+// A phase updates one factor by one Nesterov inner loop (Sec. 2): the G
+// update of Eq. (2) or the F update of Eq. (3), plain or compressed
+// (Sec. 3, Algorithm 1).  In row form both are
+//     min_{Z >= 0}  0.5 tr(Z W Z^T) - tr(B^T Z),   grad(Z) = Z W - B,
+// over independent rows of p unknowns: the rows of G, or the columns of F.
+//
+// Inside one launch:
+//   1. Small product.  S = sum of the partial products the previous phase
+//      left behind (compressed: S = L G or (F R)^T, l x p; plain: S = W).
+//      Workgroups split the partial sums, publish their share through
+//      tagged slots, and read everyone else's share back.
+//   2. W = S^T S (compressed) and L = lambda_max(W) in FP64, computed by
+//      every workgroup; B rows = D S with D = X R (G update) or (L X)^T
+//      (F update) on the matrix cores (plain: B from an X sweep).
+//   3. The inner loop.  Z_k = max(0, Y_k - grad(Y_k)/L), Y_{k+1} = Z_k +
+//      ((alpha_{k-1} - 1)/alpha_k)(Z_k - Z_{k-1}), stop at the first k >=
+//      inner_min with ||P grad(Z_k)||_F <= tol.  grad(Z_k) = Z_k W - B on the
+//      matrix cores, grad(Y) by linearity.  The squared projected-gradient
+//      norm of step k is summed in FP64 and published by every workgroup;
+//      the test of step k is taken DLAG steps later, so the exchange latency
+//      hides behind DLAG further steps whose results are simply discarded
+//      when step k turns out to be the last.
+//   4. The next phase's partial product over this workgroup's rows:
+//      compressed sum_r q_r (x) z_r with q_r the row of Q_L (G update) or
+//      Q_R (F update), giving L G = Q_L^T G or (F Q_R)^T; plain Z^T Z.
+//
+// Layout.  A wave owns TILES tiles of 16 rows.  Lane l holds, for row
+// 16 t + (l % 16) of its tiles, the columns c = 16 h + 4 s + l / 16,
+// h < PT, s < 4, in register (h, s).  With v_mfma_f32_16x16x4f32 computing
+// D' = A Z^T where A[m][k] = W[k][16 h' + perm(m)], perm(m) = 4 (m % 4) +
+// m / 4, the B operand of K slice (h, s) is exactly register (h, s), and the
+// output register (h', i) lands on column 16 h' + 4 i + l / 16: the product
+// Z W comes out in the layout it went in, with no data movement.
+//
+// Exchange.  Slots are 64-bit words written and read with relaxed
+// device-scope atomics: the upper 32 bits carry a tag (launch sequence and
+// step), the lower 32 bits the payload, so a reader accepts a word only when
+// its tag matches and needs no fence.  An FP64 value takes two words.
+#include "internal.hpp"
+
+namespace cnmf {
+
+namespace {
+
+constexpr int kThreads = 256;
+static_assert(kPgSlots >= 2 * 4 + 2, "slots for the largest lag");
+
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int perm16(int m) { return 4 * (m & 3) + (m >> 2); }
+
+__device__ __forceinline__ void slot_store(uint64_t* p, unsigned tag, uint32_t payload) {
+    __hip_atomic_store(p, ((uint64_t)tag << 32) | payload, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t slot_load(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// lambda_max of a symmetric p x p matrix held in LDS as doubles (destroyed),
+// by one wavefront: Householder tridiagonalisation (lane i owns row i), then
+// Sturm-sequence multisection over 64 points per round.  Returns the value
+// on every lane.
+// ---------------------------------------------------------------------------
+__device__ double lambda_max_wave(double (*A)[33], int p, double* v, double* wv, double* dg,
+                                  double* eo) {
+    const int lane = threadIdx.x & 63;
+    for (int k = 0; k + 2 < p; ++k) {
+        const int i = lane;
+        const bool in = (i > k) && (i < p);
+        const double xi = in ? A[i][k] : 0.0;
+        const double sigma = wave_sum(xi * xi);
+        const double x0 = A[k + 1][k];
+        if (sigma == 0.0) {
+            if (lane == 0) { dg[k] = A[k][k]; eo[k] = 0.0; }
+            continue;
+        }
+        const double alpha = -copysign(sqrt(sigma), x0);
+        const double v0 = x0 - alpha;
+        const double vn = sqrt(sigma - x0 * x0 + v0 * v0);
+        if (in) v[i] = ((i == k + 1) ? v0 : xi) / vn;
+        __builtin_amdgcn_wave_barrier();
+        double ui = 0.0;
+        if (in)
+            for (int j = k + 1; j < p; ++j) ui = fma(A[i][j], v[j], ui);
+        const double c = wave_sum(in ? v[i] * ui : 0.0);
+        if (in) wv[i] = 2.0 * ui - 2.0 * c * v[i];
+        __builtin_amdgcn_wave_barrier();
+        if (in)
+            for (int j = k + 1; j < p; ++j) A[i][j] -= v[i] * wv[j] + wv[i] * v[j];
+        if (lane == 0) { dg[k] = A[k][k]; eo[k] = alpha; }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0) {
+        if (p >= 2) {
+            dg[p - 2] = A[p - 2][p - 2];
+            eo[p - 2] = A[p - 1][p - 2];
+        }
+        dg[p - 1] = A[p - 1][p - 1];
+    }
+    __builtin_amdgcn_wave_barrier();
+    double lo = -INFINITY, hi = -INFINITY;
+    bool bad = false;
+    for (int i = 0; i < p; ++i) {
+        const double el = (i > 0) ? fabs(eo[i - 1]) : 0.0;
+        const double er = (i + 1 < p) ? fabs(eo[i]) : 0.0;
+        lo = fmax(lo, dg[i]);
+        hi = fmax(hi, dg[i] + el + er);
+        if (!isfinite(dg[i]) || !isfinite(er)) bad = true;
+    }
+    if (bad) return NAN;
+    if (!(hi > 0.0)) return fmax(lo, 0.0);
+    // Scale to [.., 1] so the pivots stay O(1).
+    const double sc = 1.0 / hi;
+    double l0 = lo * sc, h0 = 1.0;
+    const double pivmin = 1e-300;
+    for (int round = 0; round < 12 && h0 > l0; ++round) {
+        const double x = l0 + (h0 - l0) * (double)(lane + 1) / 65.0;
+        int cnt = 0;   // eigenvalues of T/hi below x (negative LDL^T pivots)
+        double q = dg[0] * sc - x;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+        for (int i = 1; i < p; ++i) {
+            const double e = eo[i - 1] * sc;
+            double r = __builtin_amdgcn_rcp(q);     // 1/q to full precision:
+            r = fma(r, fma(-q, r, 1.0), r);         // two Newton steps on the
+            r = fma(r, fma(-q, r, 1.0), r);         // hardware estimate
+            q = (dg[i] * sc - x) - e * e * r;
+            if (fabs(q) < pivmin) q = -pivmin;
+            cnt += q < 0.0;
+        }
+        const unsigned long long mask = __ballot(cnt == p);   // lambda_max < x
+        double nlo = l0, nhi = h0;
+        if (mask) {
+            const int first = __ffsll((long long)mask) - 1;
+            nhi = __shfl(x, first, 64);
+            if (first > 0) nlo = __shfl(x, first - 1, 64);
+        } else {
+            nlo = __shfl(x, 63, 64);
+        }
+        if (!(nhi - nlo < h0 - l0)) break;
+        l0 = nlo;
+        h0 = nhi;
+        if (h0 - l0 <= 1e-13 * h0) break;
+    }
+    return h0 * hi;
+}
+
+}  // namespace
+
+namespace {
+
+template <int PT, int TILES, int DLAG>
+__global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
+    constexpr int NH = (DLAG + 1) > 2 ? (DLAG + 1) : 2;     // iterates kept
+    constexpr int NR = PT * 4;                              // registers per row tile
+    constexpr int NSLOT = 2 * DLAG + 2;
+    __shared__ float sS[32][33];      // S (rows: M index, cols: p)
+    __shared__ float sW[32][33];      // W (p x p)
+    __shared__ double sA[32][33];     // FP64 W for lambda_max
+    __shared__ double sv[32], swv[32], sdg[32], seo[32];
+    __shared__ double s_red[4];
+    __shared__ double s_tot;
+    __shared__ double s_L;
+    __shared__ int s_flag;
+    __shared__ float zt[4][16][33];   // per-wave transpose tile
+    __shared__ float sred[4][16][64]; // epilogue reduction
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int q16 = lane & 15;
+    const int g4 = lane >> 4;
+    const unsigned nblk = gridDim.x;
+    const int p = a.p;
+    Control* ctl = a.ctl;
+    bool ok = true;
+
+    // ---------------- 1. small product S ------------------------------------
+    const int Srows = (a.mode == 2) ? a.ell : p;
+    const int nS = Srows * p;
+    for (int e = threadIdx.x; e < 32 * 33; e += kThreads) {
+        sS[e / 33][e % 33] = 0.f;
+        sW[e / 33][e % 33] = 0.f;
+    }
+    __syncthreads();
+    if (a.mode == 0) {
+        for (int e = threadIdx.x; e < p * p; e += kThreads) sW[e / p][e % p] = a.Wgiven[e];
+    } else if (a.kind != 2) {
+        // this workgroup's share: entries e = blockIdx.x + nblk * j, one wave each
+        for (int e = blockIdx.x + nblk * wave; e < nS; e += nblk * 4) {
+            const int mr = e / p, nc = e % p;
+            double t = 0.0;
+            for (int j = lane; j < a.nin; j += 64) t += (double)a.part_in[(size_t)j * 1024 + mr * 32 + nc];
+            t = wave_sum(t);
+            if (lane == 0) slot_store(&a.slot_s[e], a.seq, __float_as_uint((float)t));
+        }
+        // read all shares back
+        unsigned spins = 0;
+        for (;;) {
+            int mine_ok = 1;
+            for (int e = threadIdx.x; e < nS; e += kThreads) {
+                const uint64_t w = slot_load(&a.slot_s[e]);
+                if ((unsigned)(w >> 32) == a.seq) sS[e / p][e % p] = __uint_as_float((uint32_t)w);
+                else mine_ok = 0;
+            }
+            if (__syncthreads_and(mine_ok)) break;
+            __builtin_amdgcn_s_sleep(1);
+            ++spins;
+            int to = 0;
+            if (threadIdx.x == 0 && (spins & 255u) == 0u)
+                to = spins >= (kSpinLimit >> 4) || (atomic_status_load(&ctl->status) & CNMF_ST_TIMEOUT);
+            if (__syncthreads_or(to)) {
+                if (threadIdx.x == 0) raise_status(ctl, CNMF_ST_TIMEOUT);
+                ok = false;
+                break;
+            }
+        }
+        if (a.mode == 1) {
+            for (int e = threadIdx.x; e < p * p; e += kThreads) sW[e / p][e % p] = sS[e / p][e % p];
+        } else {
+            // W = S^T S (l x p -> p x p), FP64 accumulation
+            for (int e = threadIdx.x; e < p * p; e += kThreads) {
+                const int i = e / p, j = e % p;
+                double t = 0.0;
+                for (int k = 0; k < a.ell; ++k) t = fma((double)sS[k][i], (double)sS[k][j], t);
+                sW[i][j] = (float)t;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---------------- 2. Lipschitz constant (wave 0), B rows, Z rows --------
+    double L = 1.0;
+    if (a.kind == 0) {
+        if (wave == 0) {
+            for (int e = lane; e < p * p; e += 64) {
+                const int i = e / p, j = e % p;
+                sA[i][j] = 0.5 * ((double)sW[i][j] + (double)sW[j][i]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const double lm = lambda_max_wave(sA, p, sv, swv, sdg, seo);
+            if (lane == 0) s_L = lm;
+        }
+    }
+
+    // A operand of the gradient product: W[k][16h' + perm(m)] (Z W) or its
+    // transpose (Z W^T), k = 16 h + 4 s + l / 16, m = l % 16.
+    float wA[PT][PT][4];
+#pragma unroll
+    for (int hp = 0; hp < PT; ++hp)
+#pragma unroll
+        for (int h = 0; h < PT; ++h)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = 16 * h + 4 * s + g4;
+                const int c = 16 * hp + perm16(q16);
+                wA[hp][h][s] = a.wt ? sW[c][k] : sW[k][c];
+            }
+
+    const int64_t row_base = (int64_t)blockIdx.x * (64 * TILES) + (int64_t)wave * (16 * TILES);
+    float z[TILES][NR], bb[TILES][NR];
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+        const int64_t r = row_base + 16 * t + q16;
+        const bool act = r < a.rows;
+#pragma unroll
+        for (int h = 0; h < PT; ++h)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int c = 16 * h + 4 * s + g4;
+                const bool in = act && c < p;
+                z[t][4 * h + s] = in ? a.Z[r * a.z_rs + c * a.z_cs] : 0.f;
+                if (a.mode != 2) bb[t][4 * h + s] = in ? a.Bgiven[r * p + c] : 0.f;
+            }
+        if (a.mode == 2) {
+            // B rows = D S: A operand S[k][16h' + perm(m)], B operand D[r][k]
+#pragma unroll
+            for (int hp = 0; hp < PT; ++hp) {
+                v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int k = 16 * hk + 4 * s + g4;
+                        const int c = 16 * hp + perm16(q16);
+                        const float av = (k < a.ell && c < p) ? sS[k][c] : 0.f;
+                        const float dv = (act && k < a.ell) ? a.D[r * a.d_rs + k * a.d_cs] : 0.f;
+                        acc = mfma16(av, dv, acc);
+                    }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) bb[t][4 * hp + i] = acc[i];
+            }
+        }
+    }
+
+    auto grad = [&](const float (&zz)[NR], const float (&b)[NR], float (&g)[NR]) {
+#pragma unroll
+        for (int hp = 0; hp < PT; ++hp) {
+            v4f acc = {-b[4 * hp + 0], -b[4 * hp + 1], -b[4 * hp + 2], -b[4 * hp + 3]};
+#pragma unroll
+            for (int h = 0; h < PT; ++h)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc = mfma16(wA[hp][h][s], zz[4 * h + s], acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) g[4 * hp + i] = acc[i];
+        }
+    };
+    auto pg2_of = [&](const float (&zz)[NR], const float (&g)[NR]) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const float pg = (zz[i] > 0.f) ? g[i] : fminf(g[i], 0.f);
+            const double d = (g[i] != g[i]) ? (double)g[i] : (double)pg;
+            sacc = fma(d, d, sacc);
+        }
+        return sacc;
+    };
+    // workgroup sum of one double per thread, published as step `step`
+    auto publish = [&](double v, int step) {
+        v = wave_sum(v);
+        if (lane == 0) s_red[wave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double tot = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+            const uint64_t bits = (uint64_t)__double_as_longlong(tot);
+            const unsigned tag = (a.seq << 10) | ((unsigned)step & 1023u);
+            uint64_t* sl = a.slot_pg + ((size_t)(step % NSLOT) * 256 + blockIdx.x) * 2;
+            slot_store(sl + 0, tag, (uint32_t)(bits >> 32));
+            slot_store(sl + 1, tag, (uint32_t)(bits & 0xffffffffu));
+        }
+    };
+    // grid total of step `step` (wave 0 polls; result broadcast through LDS)
+    auto collect = [&](int step) -> double {
+        if (wave == 0) {
+            const unsigned tag = (a.seq << 10) | ((unsigned)step & 1023u);
+            const uint64_t* base = a.slot_pg + (size_t)(step % NSLOT) * 256 * 2;
+            unsigned spins = 0;
+            int to = 0;
+            double t = 0.0;
+            for (;;) {
+                int mine_ok = 1;
+                t = 0.0;
+                for (unsigned i = lane; i < nblk; i += 64) {
+                    const uint64_t w0 = slot_load(base + 2 * i);
+                    const uint64_t w1 = slot_load(base + 2 * i + 1);
+                    if ((unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag)
+                        t += __longlong_as_double((long long)((w0 << 32) | (w1 & 0xffffffffu)));
+                    else
+                        mine_ok = 0;
+                }
+                if (__all(mine_ok)) break;
+                __builtin_amdgcn_s_sleep(1);
+                ++spins;
+                int t0 = 0;
+                if ((spins & 255u) == 0u)
+                    t0 = spins >= (kSpinLimit >> 4) ||
+                         (atomic_status_load(&ctl->status) & CNMF_ST_TIMEOUT);
+                if (__any(t0)) { to = 1; break; }
+            }
+            t = wave_sum(t);
+            if (lane == 0) {
+                s_tot = t;
+                s_flag = to;
+                if (to) raise_status(ctl, CNMF_ST_TIMEOUT);
+            }
+        }
+        __syncthreads();
+        return s_tot;
+    };
+
+    float g[TILES][NR];
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) grad(z[t], bb[t], g[t]);
+
+    __syncthreads();   // s_L
+    L = (a.kind == 0) ? s_L : 1.0;
+
+    const bool need_pg0 = a.kind != 2 && (a.kind == 1 || a.pg2_out != nullptr || a.ratio > 0.0);
+    double pg0 = 0.0;
+    if (need_pg0 && ok) {
+        double v = 0.0;
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) v += pg2_of(z[t], g[t]);
+        publish(v, 0);
+        pg0 = collect(0);
+        if (s_flag) ok = false;
+    }
+
+    double tol = a.tol_ptr ? *a.tol_ptr : a.tol_value;
+    if (a.ratio > 0.0 && a.kind == 0) tol = a.ratio * sqrt(pg0);
+    const int forced = a.forced_ptr ? (int)*a.forced_ptr : a.forced;
+    const int kmax = (a.kind != 0) ? 0 : (forced >= 0 ? forced : a.inner_max);
+    int steps = 0;
+
+    // zh[j] = Z_{K - j}
+    float zh[NH][TILES][NR];
+#pragma unroll
+    for (int j = 0; j < NH; ++j)
+#pragma unroll
+        for (int t = 0; t < TILES; ++t)
+#pragma unroll
+            for (int i = 0; i < NR; ++i) zh[j][t][i] = z[t][i];
+    int out_idx = 0;
+
+    if (!(L > 0.0)) {
+        if (a.kind == 0 && blockIdx.x == 0 && threadIdx.x == 0)
+            raise_status(ctl, (L != L) ? CNMF_ST_NONFINITE : CNMF_ST_ZERO_LIPS);
+    } else if (ok && kmax > 0) {
+        const float invL = (float)(1.0 / L);
+        float gp[TILES][NR];
+#pragma unroll
+        for (int t = 0; t < TILES; ++t)
+#pragma unroll
+            for (int i = 0; i < NR; ++i) gp[t][i] = g[t][i];
+        double alpha = 1.0;
+        float beta = 0.f;
+        const bool check = forced < 0;
+        const int kend = check ? kmax + DLAG : kmax;
+        int stop_at = -1;
+        int K = 1;
+        for (; K <= kend; ++K) {
+            if (K <= kmax) {
+                float zn[TILES][NR], gn[TILES][NR];
+#pragma unroll
+                for (int t = 0; t < TILES; ++t) {
+#pragma unroll
+                    for (int i = 0; i < NR; ++i) {
+                        const float y = fmaf(beta, zh[0][t][i] - zh[1][t][i], zh[0][t][i]);
+                        const float gy = fmaf(beta, g[t][i] - gp[t][i], g[t][i]);
+                        const float v = fmaf(-gy, invL, y);
+                        zn[t][i] = (v > 0.f || v != v) ? v : 0.f;
+                    }
+                    grad(zn[t], bb[t], gn[t]);
+                }
+                const double alpha_n = 0.5 * (1.0 + sqrt(4.0 * alpha * alpha + 1.0));
+                beta = (float)((alpha - 1.0) / alpha_n);
+                alpha = alpha_n;
+#pragma unroll
+                for (int j = NH - 1; j >= 1; --j)
+#pragma unroll
+                    for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                        for (int i = 0; i < NR; ++i) zh[j][t][i] = zh[j - 1][t][i];
+#pragma unroll
+                for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                    for (int i = 0; i < NR; ++i) {
+                        zh[0][t][i] = zn[t][i];
+                        gp[t][i] = g[t][i];
+                        g[t][i] = gn[t][i];
+                    }
+                if (check && K >= a.inner_min) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int t = 0; t < TILES; ++t) v += pg2_of(zh[0][t], g[t]);
+                    publish(v, K);
+                }
+            } else {
+                // past the budget: keep zh[j] = Z_{K-j} for the steps still to test
+#pragma unroll
+                for (int j = NH - 1; j >= 1; --j)
+#pragma unroll
+                    for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                        for (int i = 0; i < NR; ++i) zh[j][t][i] = zh[j - 1][t][i];
+            }
+            if (check) {
+                const int jst = K - DLAG;
+                if (jst >= a.inner_min && jst <= kmax) {
+                    const double tot = collect(jst);
+                    if (s_flag) { ok = false; break; }
+                    if (!(tot == tot)) {
+                        if (blockIdx.x == 0 && threadIdx.x == 0) raise_status(ctl, CNMF_ST_NONFINITE);
+                    } else if (sqrt(tot) <= tol) {
+                        stop_at = jst;
+                        break;
+                    }
+                }
+            }
+        }
+        if (K > kend) K = kend;
+        steps = stop_at >= 0 ? stop_at : kmax;
+        out_idx = K - steps;   // 0 .. DLAG
+    }
+
+    // final iterate zh[out_idx] -> z
+#pragma unroll
+    for (int j = 0; j < NH; ++j)
+        if (j == out_idx)
+#pragma unroll
+            for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                for (int i = 0; i < NR; ++i) z[t][i] = zh[j][t][i];
+
+    // ---------------- 4. write back, next phase's partial product ----------
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+        const int64_t r = row_base + 16 * t + q16;
+        if (r < a.rows && a.kind == 0) {
+#pragma unroll
+            for (int h = 0; h < PT; ++h)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int c = 16 * h + 4 * s + g4;
+                    if (c < p) {
+                        a.Z[r * a.z_rs + c * a.z_cs] = z[t][4 * h + s];
+                        if (a.hist) a.hist[r * a.z_rs + c * a.z_cs] = z[t][4 * h + s];
+                    }
+                }
+        }
+    }
+    if (a.part_out) {
+        // partial = sum over rows of q_r (x) z_r (mode 2, l x p) or z_r (x) z_r (p x p)
+        constexpr int MT = 2;   // M tiles (l <= 32 or p <= 32)
+        v4f acc[MT][PT];
+#pragma unroll
+        for (int hm = 0; hm < MT; ++hm)
+#pragma unroll
+            for (int hn = 0; hn < PT; ++hn) acc[hm][hn] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) {
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int h = 0; h < PT; ++h)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) zt[wave][q16][16 * h + 4 * s + g4] = z[t][4 * h + s];
+            if (PT == 1)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) zt[wave][q16][16 + 4 * s + g4] = 0.f;
+            __builtin_amdgcn_wave_barrier();
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int rr = 4 * s + g4;                 // row within the tile (K index)
+                const int64_t r = row_base + 16 * t + rr;
+                float bv[PT];
+#pragma unroll
+                for (int hn = 0; hn < PT; ++hn) bv[hn] = zt[wave][rr][16 * hn + q16];
+#pragma unroll
+                for (int hm = 0; hm < MT; ++hm) {
+                    float av;
+                    if (a.mode == 2) {
+                        const int k = 16 * hm + q16;
+                        av = (r < a.rows && k < a.ell) ? a.Q[r * a.ell + k] : 0.f;
+                    } else {
+                        av = (hm < PT) ? zt[wave][rr][16 * hm + q16] : 0.f;
+                    }
+#pragma unroll
+                    for (int hn = 0; hn < PT; ++hn) acc[hm][hn] = mfma16(av, bv[hn], acc[hm][hn]);
+                }
+            }
+            __syncthreads();
+        }
+        // reduce the 4 waves: element (M = 16 hm + 4 g4 + i, N = 16 hn + q16)
+#pragma unroll
+        for (int hm = 0; hm < MT; ++hm)
+#pragma unroll
+            for (int hn = 0; hn < PT; ++hn)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sred[wave][(hm * 2 + hn) * 4 + i][lane] = acc[hm][hn][i];
+        __syncthreads();
+        for (int e = threadIdx.x; e < 16 * 64; e += kThreads) {
+            const int ri = e / 64, l = e % 64;
+            const int hm = (ri / 4) / 2, hn = (ri / 4) % 2, i = ri % 4;
+            const int M = 16 * hm + 4 * (l >> 4) + i;
+            const int N = 16 * hn + (l & 15);
+            const float s = (sred[0][ri][l] + sred[1][ri][l]) + (sred[2][ri][l] + sred[3][ri][l]);
+            if (hn < PT) a.part_out[(size_t)blockIdx.x * 1024 + M * 32 + N] = s;
+            else a.part_out[(size_t)blockIdx.x * 1024 + M * 32 + N] = 0.f;
+        }
+    }
+
+    if (threadIdx.x == 0) {
+        if (blockIdx.x == 0) {
+            if (a.steps_out && a.kind == 0) a.steps_out[0] = steps;
+            if (a.L_out) a.L_out[0] = L;
+            if (a.tol_out) a.tol_out[0] = tol;
+            if (a.pg2_out) a.pg2_out[0] = pg0;
+            if (a.kind == 1 && a.tol_init_from) {
+                const double tt = a.ratio * sqrt(pg0 + *a.tol_init_from);
+                ctl->tol[0] = tt;
+                ctl->tol[1] = tt;
+                if (!isfinite(tt)) raise_status(ctl, CNMF_ST_NONFINITE);
+            }
+            if (a.kind == 0 && a.tol_state && steps >= 1 && steps <= a.inner_min)
+                a.tol_state[0] = tol / 10.0;
+        }
+        if (a.tick_out) atomicMax(a.tick_out, (unsigned long long)wall_clock64());
+    }
+}
+
+template <int PT, int TILES, int DLAG>
+hipError_t launch3(const Dev& d, const PhaseArgs& a, unsigned nblk) {
+    hipLaunchKernelGGL((k_phase<PT, TILES, DLAG>), dim3(nblk), dim3(kThreads), 0, d.stream, a);
+    return hipGetLastError();
+}
+
+template <int PT, int TILES>
+hipError_t launch2(const Dev& d, const PhaseArgs& a, unsigned nblk) {
+    switch (a.dlag) {
+        case 0: return launch3<PT, TILES, 0>(d, a, nblk);
+        case 1: return launch3<PT, TILES, 1>(d, a, nblk);
+        case 2: return launch3<PT, TILES, 2>(d, a, nblk);
+        case 3: return launch3<PT, TILES, 3>(d, a, nblk);
+        default: return launch3<PT, TILES, 4>(d, a, nblk);
+    }
+}
+
+template <int PT>
+hipError_t launch1(const Dev& d, const PhaseArgs& a, int tiles, unsigned nblk) {
+    switch (tiles) {
+        case 1: return launch2<PT, 1>(d, a, nblk);
+        case 2: return launch2<PT, 2>(d, a, nblk);
+        default: return launch2<PT, 4>(d, a, nblk);
+    }
+}
+
+}  // namespace
+
+// Rows per workgroup and grid for `rows` rows: the grid must fit on the CUs
+// at once (workgroups wait for each other's partial norms).
+bool phase_grid(const Dev& d, int64_t rows, int* tiles, unsigned* nblk) {
+    for (int t : {1, 2, 4}) {
+        const int64_t nb = (rows + 64 * t - 1) / (64 * t);
+        if (nb <= d.num_cus && nb <= 256) {
+            *tiles = t;
+            *nblk = (unsigned)(nb < 1 ? 1 : nb);
+            return true;
+        }
+    }
+    return false;
+}
+
+hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles) {
+    if (a.p < 1 || a.p > 32 || a.dlag < 0 || a.dlag > 4) return hipErrorInvalidValue;
+    if (a.p <= 16) return launch1<1>(d, a, tiles, nblk);
+    return launch1<2>(d, a, tiles, nblk);
+}
+
+// lambda_max of a p x p FP32 matrix, one wavefront (kernel-level entry point).
+namespace {
+__global__ __launch_bounds__(64) void k_lips(int p, const float* __restrict__ W,
+                                             double* __restrict__ out, Control* ctl) {
+    __shared__ double A[32][33];
+    __shared__ double v[32], wv[32], dg[32], eo[32];
+    for (int e = threadIdx.x; e < p * p; e += 64) {
+        const int i = e / p, j = e % p;
+        A[i][j] = 0.5 * ((double)W[i * p + j] + (double)W[j * p + i]);
+    }
+    __syncthreads();
+    const double lm = lambda_max_wave(A, p, v, wv, dg, eo);
+    if (threadIdx.x == 0) {
+        out[0] = lm;
+        if (lm != lm) raise_status(ctl, CNMF_ST_NONFINITE);
+    }
+}
+}  // namespace
+
+hipError_t lipschitz(const Dev& d, int p, const float* W, double* out, Control* ctl) {
+    hipLaunchKernelGGL(k_lips, dim3(1), dim3(64), 0, d.stream, p, W, out, ctl);
+    return hipGetLastError();
+}
+
+}  // namespace cnmf
