@@ -12,6 +12,8 @@
 // workgroup row of the grid; the 4 waves of a workgroup reduce through LDS
 // and each workgroup writes one partial tile.  A second kernel sums the S
 // partials in a fixed order, so results are bitwise reproducible.
+#include <cstdlib>
+
 #include "internal.hpp"
 
 namespace cnmf {
@@ -29,265 +31,511 @@ __device__ __forceinline__ int acc_row(int r, int lane) {
     return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
 }
 
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 // ---------------------------------------------------------------------------
-// Right sweep.  Workgroup = 32 rows of X; its 4 waves take interleaved
-// 32-column chunks of the workgroup's K slice.  Lane l holds row (l % 32)
-// and the 16 consecutive columns starting at chunk + 16 (l / 32); element s
-// feeds MFMA s, whose K index (l / 32) therefore stands for column
-// chunk + 16 (l / 32) + s.  The B operand of MFMA s is A at that column
-// (row of A) and output column l % 32.
+// Right sweep, Y = X A.  Workgroup = 32 rows of X times one K slice.
+// X is streamed in stages of 32 rows x SW columns: each wave reads 8 rows
+// of it, a contiguous kilobyte per instruction (one row when SW = 256, two
+// half rows when SW = 128), into LDS; the next stage is loaded into
+// registers while the current one is multiplied.  Wave w multiplies the
+// quarter KW = SW / 4 columns starting at KW w.
+//   NT = 32 (k > 16): v_mfma_f32_32x32x2f32.  Lane l reads row l % 32 and NA
+//     consecutive columns starting at KW w + NA (l / 32); MFMA s uses element
+//     s, so its K index (l / 32) stands for that start + s, and its B operand
+//     is A at that column and output column l % 32.
+//   NT = 16 (k <= 16): v_mfma_f32_16x16x4f32 on two 16-row tiles, lane l at
+//     rows l % 16 and 16 + l % 16, columns KW w + NA (l / 16) + s.
+// The four waves' partial sums are added through LDS at the end.
 // ---------------------------------------------------------------------------
-template <bool A_T, bool VEC, bool DIRECT>
+template <int NT, int SW>
+struct RightShape {
+    static constexpr int KW = SW / 4;                 // K columns per wave per stage
+    static constexpr int KL = NT == 32 ? 2 : 4;       // K lane groups of the MFMA
+    static constexpr int NA = KW / KL;                // A values per lane per stage
+    static constexpr int PITCH = SW + 4;              // LDS row pitch (bank spread)
+    static constexpr int XV = SW / 32;                // float4 X loads per lane per stage
+};
+
+template <int NT, int SW, bool A_T, bool VEC>
+__device__ __forceinline__ void right_load_a(const float* __restrict__ A, int64_t lda, int k,
+                                             int64_t K0, int lane, float (&a)[RightShape<NT, SW>::NA]) {
+    constexpr int NA = RightShape<NT, SW>::NA;
+    const int n = NT == 32 ? (lane & 31) : (lane & 15);
+    const int nc = n < k ? n : 0;
+    if (A_T && VEC) {
+        const v4f* p = reinterpret_cast<const v4f*>(A + nc * lda + K0);
+#pragma unroll
+        for (int t = 0; t < NA / 4; ++t) {
+            const v4f v = p[t];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[4 * t + u] = v[u];
+        }
+    } else if (A_T) {
+#pragma unroll
+        for (int s = 0; s < NA; ++s) a[s] = A[nc * lda + K0 + s];
+    } else {
+#pragma unroll
+        for (int s = 0; s < NA; ++s) a[s] = A[(K0 + s) * lda + nc];
+    }
+}
+
+template <int NT, int SW, bool A_T, bool DIRECT, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_sweep_right(
     int64_t R, int64_t C, const float* __restrict__ X, int64_t ldx, int k,
     const float* __restrict__ A, int64_t lda, float* __restrict__ out, int64_t ldo,
-    int64_t chunks_per_split) {
-    __shared__ float red[4][16][kWave];
+    int64_t span) {
+    using Sh = RightShape<NT, SW>;
+    constexpr int KW = Sh::KW, NA = Sh::NA, PITCH = Sh::PITCH, XV = Sh::XV;
+    __shared__ __attribute__((aligned(16))) float xs[32 * PITCH > 4096 ? 32 * PITCH : 4096];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int mr = lane & 31;
-    const int kh = lane >> 5;
     const int64_t row0 = (int64_t)blockIdx.x * 32;
-    const int64_t nchunks = (C + 31) / 32;
-    const int64_t c_begin = (int64_t)blockIdx.y * chunks_per_split;
-    const int64_t c_end = min(nchunks, c_begin + chunks_per_split);
-    const int64_t xrow = row0 + mr;
-    const bool rowok = xrow < R;
-    const float* xr = X + (rowok ? xrow : 0) * ldx;
-    const bool colok = mr < k;
-    const float* ar = A_T ? A + (colok ? mr : 0) * lda : A + (colok ? mr : 0);
+    const int64_t c_lo = (int64_t)blockIdx.y * span;
+    const int64_t c_hi = min(C, c_lo + span);
+    const int64_t nst = (c_hi - c_lo + SW - 1) / SW;
+    const int koff = KW * wave + NA * (NT == 32 ? (lane >> 5) : (lane >> 4));
+    // X loads: instruction rr covers row 8 w + rr (SW = 256) or rows
+    // 8 w + 2 rr + l / 32 (SW = 128); lane column offset within the stage:
+    const int xrow_l = SW == 256 ? 0 : (lane >> 5);
+    const int xcol_l = SW == 256 ? 4 * lane : 4 * (lane & 31);
+    const int xrow_step = SW == 256 ? 1 : 2;
 
-    v16f acc;
+    v16f acc32;
+    v4f acc16[2];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int r = 0; r < 16; ++r) acc32[r] = 0.f;
+    acc16[0] = acc16[1] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t ch = c_begin + wave; ch < c_end; ch += 4) {
-        const int64_t j0 = ch * 32 + kh * 16;
-        float xv[16], av[16];
-        const bool full = (j0 + 16 <= C);
-        if (VEC && full) {
-            const v4f* p = reinterpret_cast<const v4f*>(xr + j0);
+    v4f xn[XV];
+    float an[NA], ac[NA];
+    // Full stages (inside the slice, aligned rows) use plain vector loads;
+    // a ragged last stage, or unaligned rows, use clamped scalar loads that
+    // zero what lies past the slice.  The two never share a loop, so the
+    // pipelined loop has a single load path and nothing waits early.
+    const int64_t nfull = VEC ? (c_hi - c_lo) / SW : 0;
+    auto load_fast = [&](int64_t st) {
+        st = st < nfull ? st : nfull - 1;
+        const int64_t cb = c_lo + SW * st;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                v4f v = rowok ? p[t] : v4f{0.f, 0.f, 0.f, 0.f};
-                xv[4 * t + 0] = v[0]; xv[4 * t + 1] = v[1];
-                xv[4 * t + 2] = v[2]; xv[4 * t + 3] = v[3];
+        for (int rr = 0; rr < XV; ++rr) {
+            const int64_t row = row0 + 8 * wave + xrow_step * rr + xrow_l;
+            const float* xr = X + (row < R ? row : R - 1) * ldx;
+            xn[rr] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(xr + cb + xcol_l));
+        }
+        right_load_a<NT, SW, A_T, VEC>(A, lda, k, cb + koff, lane, an);
+    };
+    auto load_slow = [&](int64_t st) {
+        const int64_t cb = c_lo + SW * st;
+        const int64_t K0 = cb + koff;
+#pragma unroll
+        for (int rr = 0; rr < XV; ++rr) {
+            const int64_t row = row0 + 8 * wave + xrow_step * rr + xrow_l;
+            const float* xr = X + (row < R ? row : R - 1) * ldx;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t c = cb + xcol_l + u;
+                const float v = xr[c < c_hi ? c : c_hi - 1];
+                xn[rr][u] = c < c_hi ? v : 0.f;
+            }
+        }
+        const int n = NT == 32 ? (lane & 31) : (lane & 15);
+        const int nc = n < k ? n : 0;
+#pragma unroll
+        for (int s = 0; s < NA; ++s) {
+            const int64_t kk = K0 + s;
+            const int64_t kc = kk < c_hi ? kk : c_hi - 1;
+            const float v = A_T ? A[nc * lda + kc] : A[kc * lda + nc];
+            an[s] = kk < c_hi ? v : 0.f;
+        }
+    };
+    auto store_stage = [&]() {
+#pragma unroll
+        for (int rr = 0; rr < XV; ++rr)
+            *reinterpret_cast<v4f*>(&xs[(8 * wave + xrow_step * rr + xrow_l) * PITCH + xcol_l]) = xn[rr];
+#pragma unroll
+        for (int s = 0; s < NA; ++s) ac[s] = an[s];
+    };
+    auto compute = [&]() {
+        if (NT == 32) {
+            const float* xr = &xs[(lane & 31) * PITCH + koff];
+#pragma unroll
+            for (int t = 0; t < NA / 4; ++t) {
+                const v4f v = *reinterpret_cast<const v4f*>(xr + 4 * t);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc32 = mfma32(v[u], ac[4 * t + u], acc32);
             }
         } else {
 #pragma unroll
-            for (int s = 0; s < 16; ++s)
-                xv[s] = (rowok && j0 + s < C) ? xr[j0 + s] : 0.f;
-        }
-        if (A_T) {
-            if (VEC && full) {
-                const v4f* p = reinterpret_cast<const v4f*>(ar + j0);
+            for (int t = 0; t < NA / 4; ++t) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    v4f v = colok ? p[t] : v4f{0.f, 0.f, 0.f, 0.f};
-                    av[4 * t + 0] = v[0]; av[4 * t + 1] = v[1];
-                    av[4 * t + 2] = v[2]; av[4 * t + 3] = v[3];
+                for (int mt = 0; mt < 2; ++mt) {
+                    const v4f v = *reinterpret_cast<const v4f*>(
+                        &xs[(16 * mt + (lane & 15)) * PITCH + koff + 4 * t]);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc16[mt] = mfma16(v[u], ac[4 * t + u], acc16[mt]);
                 }
-            } else {
-#pragma unroll
-                for (int s = 0; s < 16; ++s)
-                    av[s] = (colok && j0 + s < C) ? ar[j0 + s] : 0.f;
             }
-        } else {
-#pragma unroll
-            for (int s = 0; s < 16; ++s)
-                av[s] = (colok && j0 + s < C) ? ar[(j0 + s) * lda] : 0.f;
         }
-#pragma unroll
-        for (int s = 0; s < 16; ++s) acc = mfma32(xv[s], av[s], acc);
-    }
+    };
 
-#pragma unroll
-    for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[r];
+    if (nfull > 0) {
+        load_fast(0);
+        store_stage();
+        __syncthreads();
+        for (int64_t st = 0; st < nfull; ++st) {
+            load_fast(st + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            compute();
+            __builtin_amdgcn_sched_barrier(0);
+            __syncthreads();
+            store_stage();
+            __syncthreads();
+        }
+    }
+    for (int64_t st = nfull; st < nst; ++st) {
+        __syncthreads();
+        load_slow(st);
+        store_stage();
+        __syncthreads();
+        compute();
+    }
     __syncthreads();
-    for (int e = threadIdx.x; e < 16 * kWave; e += kThreads) {
-        const int r = e / kWave, l = e % kWave;
-        const float s = (red[0][r][l] + red[1][r][l]) + (red[2][r][l] + red[3][r][l]);
-        const int col = l & 31;
-        const int64_t row = row0 + acc_row(r, l);
+
+    // Sum the four waves through LDS (reusing the stage buffer).
+    float* red = xs;
+    if (NT == 32) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[(wave * 16 + r) * 64 + lane] = acc32[r];
+    } else {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[(wave * 16 + mt * 4 + i) * 64 + lane] = acc16[mt][i];
+    }
+    __syncthreads();
+    // NT = 32: 16 accumulator registers per lane; NT = 16: 2 tiles x 4.
+    constexpr int NREG = NT == 32 ? 16 : 8;
+    for (int e = threadIdx.x; e < NREG * 64; e += kThreads) {
+        const int r = e / 64, l = e % 64;
+        const float s = (red[r * 64 + l] + red[(16 + r) * 64 + l]) +
+                        (red[(32 + r) * 64 + l] + red[(48 + r) * 64 + l]);
+        int col, rloc;
+        if (NT == 32) {
+            col = l & 31;
+            rloc = acc_row(r, l);
+        } else {
+            col = l & 15;
+            rloc = 16 * (r >> 2) + 4 * (l >> 4) + (r & 3);
+        }
+        const int64_t row = row0 + rloc;
         if (row < R) {
             if (DIRECT) {
                 if (col < k) out[row * ldo + col] = s;
             } else {
-                out[((int64_t)blockIdx.y * R + row) * 32 + col] = s;
+                out[((int64_t)blockIdx.y * R + row) * NT + col] = s;
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Left sweep.  Workgroup = 128 columns of X; lane l loads the 4 consecutive
-// columns 4 (l % 32) .. +3 of row i0 + (l / 32), and element t feeds the
-// MFMA of accumulator tile t, whose M index (l % 32) stands for column
-// col0 + 4 (l % 32) + t.  K runs over rows two at a time.  The 4 waves take
-// interleaved 16-row blocks of the workgroup's row slice.
+// Left sweep, Z = X^T B.  Workgroup = 256 columns of X times one row slice.
+// X is streamed in stages of 16 rows x 256 columns (each wave reads 4 rows,
+// one contiguous kilobyte per row and instruction) through LDS; the next
+// stage is in registers while the current one is multiplied.  Wave w owns
+// columns 64 w .. 64 w + 63 of the block, so no reduction across waves is
+// needed.  The M index of the MFMA is the column of X, K the row, N the
+// column of B.
+//   NT = 32: v_mfma_f32_32x32x2f32, two 32-column tiles per wave, K = 2 rows.
+//   NT = 16: v_mfma_f32_16x16x4f32, four 16-column tiles per wave, K = 4 rows.
 // ---------------------------------------------------------------------------
-template <bool VEC>
+constexpr int kLPad = 272;   // row pitch: 4-row groups of 16 floats hit distinct banks
+
+template <int NT, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_sweep_left(
     int64_t R, int64_t C, const float* __restrict__ X, int64_t ldx, int k,
-    const float* __restrict__ B, int64_t ldb, float* __restrict__ partial,
-    int64_t blocks_per_split) {
-    __shared__ float red[4][16][kWave];
+    const float* __restrict__ B, int64_t ldb, float* __restrict__ partial, int64_t rspan) {
+    __shared__ __attribute__((aligned(16))) float xs[16 * kLPad];
+    constexpr int KS = NT == 32 ? 8 : 4;        // K steps per stage
+    constexpr int MT = NT == 32 ? 2 : 4;        // M tiles per wave
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int jl = lane & 31;
-    const int kh = lane >> 5;
-    const int64_t col0 = (int64_t)blockIdx.x * 128;
-    const int64_t cb = col0 + 4 * jl;
-    const int64_t nblocks = (R + 15) / 16;
-    const int64_t b_begin = (int64_t)blockIdx.y * blocks_per_split;
-    const int64_t b_end = min(nblocks, b_begin + blocks_per_split);
-    const bool bcol = jl < k;
-    const bool full4 = cb + 4 <= C;
+    const int64_t col0 = (int64_t)blockIdx.x * 256;
+    const int64_t r_lo = (int64_t)blockIdx.y * rspan;
+    const int64_t r_hi = min(R, r_lo + rspan);
+    const int64_t nst = (r_hi - r_lo + 15) / 16;
+    const int n = NT == 32 ? (lane & 31) : (lane & 15);
+    const int nc = n < k ? n : 0;
+    const int kl = NT == 32 ? (lane >> 5) : (lane >> 4);   // K index within an MFMA
 
-    v16f acc[4];
+    v16f acc32[MT];
+    v4f acc16[MT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < MT; ++t) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+        for (int r = 0; r < 16; ++r) acc32[t][r] = 0.f;
+        acc16[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
 
-    for (int64_t rb = b_begin + wave; rb < b_end; rb += 4) {
+    v4f xn[4];
+    float bn[KS], bc[KS];
+    int64_t bn_row0 = 0, bc_row0 = 0;
+    const int64_t col = col0 + 4 * lane;
+    const bool full = VEC && col0 + 256 <= C;   // uniform across the workgroup
+    auto load_b = [&](int64_t rb) {
+        bn_row0 = rb;
 #pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            const int64_t i = rb * 16 + 2 * st + kh;
-            const bool iok = i < R;
-            const float* xr = X + (iok ? i : 0) * ldx;
-            float x0, x1, x2, x3;
-            if (VEC && full4) {
-                v4f v = iok ? *reinterpret_cast<const v4f*>(xr + cb) : v4f{0.f, 0.f, 0.f, 0.f};
-                x0 = v[0]; x1 = v[1]; x2 = v[2]; x3 = v[3];
-            } else {
-                x0 = (iok && cb + 0 < C) ? xr[cb + 0] : 0.f;
-                x1 = (iok && cb + 1 < C) ? xr[cb + 1] : 0.f;
-                x2 = (iok && cb + 2 < C) ? xr[cb + 2] : 0.f;
-                x3 = (iok && cb + 3 < C) ? xr[cb + 3] : 0.f;
+        for (int s = 0; s < KS; ++s) {
+            const int64_t row = rb + (NT == 32 ? 2 : 4) * s + kl;
+            bn[s] = B[(row < R ? row : R - 1) * ldb + nc];
+        }
+    };
+    auto load_fast = [&](int64_t st) {
+        st = st < nst ? st : nst - 1;
+        const int64_t rb = r_lo + 16 * st;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int64_t row = rb + 4 * wave + rr;
+            const float* xr = X + (row < R ? row : R - 1) * ldx;
+            xn[rr] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(xr + col));
+        }
+        load_b(rb);
+    };
+    auto load_slow = [&](int64_t st) {
+        const int64_t rb = r_lo + 16 * st;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int64_t row = rb + 4 * wave + rr;
+            const float* xr = X + (row < R ? row : R - 1) * ldx;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t c = col + u;
+                const float v = xr[c < C ? c : C - 1];
+                xn[rr][u] = c < C ? v : 0.f;
             }
-            const float bv = (iok && bcol) ? B[i * ldb + jl] : 0.f;
-            acc[0] = mfma32(x0, bv, acc[0]);
-            acc[1] = mfma32(x1, bv, acc[1]);
-            acc[2] = mfma32(x2, bv, acc[2]);
-            acc[3] = mfma32(x3, bv, acc[3]);
+        }
+        load_b(rb);
+    };
+    auto store_stage = [&]() {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+            *reinterpret_cast<v4f*>(&xs[(4 * wave + rr) * kLPad + 4 * lane]) = xn[rr];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) bc[s] = bn[s];
+        bc_row0 = bn_row0;
+    };
+    auto compute = [&]() {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int rr = (NT == 32 ? 2 : 4) * s + kl;
+            const float bv = (bc_row0 + rr < r_hi) ? bc[s] : 0.f;
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+                const float av = xs[rr * kLPad + 64 * wave + NT * t + n];
+                if (NT == 32) acc32[t] = mfma32(av, bv, acc32[t]);
+                else acc16[t] = mfma16(av, bv, acc16[t]);
+            }
+        }
+    };
+
+    if (nst > 0 && full) {
+        load_fast(0);
+        store_stage();
+        __syncthreads();
+        for (int64_t st = 0; st < nst; ++st) {
+            load_fast(st + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            compute();
+            __builtin_amdgcn_sched_barrier(0);
+            __syncthreads();
+            store_stage();
+            __syncthreads();
+        }
+    } else {
+        for (int64_t st = 0; st < nst; ++st) {
+            __syncthreads();
+            load_slow(st);
+            store_stage();
+            __syncthreads();
+            compute();
         }
     }
 
-    // Reduce the 4 waves, one accumulator tile at a time.
-    for (int t = 0; t < 4; ++t) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[t][r];
-        __syncthreads();
-        for (int e = threadIdx.x; e < 16 * kWave; e += kThreads) {
-            const int r = e / kWave, l = e % kWave;
-            const float s = (red[0][r][l] + red[1][r][l]) + (red[2][r][l] + red[3][r][l]);
-            const int c = l & 31;
-            const int64_t col = col0 + 4 * acc_row(r, l) + t;
-            if (col < C) partial[((int64_t)blockIdx.y * C + col) * 32 + c] = s;
+    for (int t = 0; t < MT; ++t) {
+        if (NT == 32) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t c = col0 + 64 * wave + 32 * t + acc_row(r, lane);
+                if (c < C) partial[((int64_t)blockIdx.y * C + c) * NT + (lane & 31)] = acc32[t][r];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t c = col0 + 64 * wave + 16 * t + 4 * (lane >> 4) + i;
+                if (c < C) partial[((int64_t)blockIdx.y * C + c) * NT + (lane & 15)] = acc16[t][i];
+            }
         }
-        __syncthreads();
     }
 }
 
-// out (rows x k) = sum over S slices of partial[s][rows][32]; optionally
+// out (rows x k) = sum over S slices of partial[s][rows][nt]; optionally
 // written transposed (k x rows).
 __global__ __launch_bounds__(kThreads) void k_reduce_slices(
-    int64_t rows, int k, int S, const float* __restrict__ partial, float* __restrict__ out,
+    int64_t rows, int k, int S, int nt, const float* __restrict__ partial, float* __restrict__ out,
     int64_t ldo, int trans) {
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (e >= rows * 32) return;
-    const int64_t r = e >> 5;
-    const int c = (int)(e & 31);
+    if (e >= rows * nt) return;
+    const int64_t r = e / nt;
+    const int c = (int)(e % nt);
     if (c >= k) return;
     float s = 0.f;
-    for (int i = 0; i < S; ++i) s += partial[((int64_t)i * rows + r) * 32 + c];
+    for (int i = 0; i < S; ++i) s += partial[((int64_t)i * rows + r) * nt + c];
     if (trans) out[(int64_t)c * ldo + r] = s;
     else out[r * ldo + c] = s;
 }
 
-bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
-
-// Number of K slices: enough workgroups to cover every CU a few times, but
-// at least 4 chunks (one per wave) per slice.
-int64_t pick_splits(int64_t tiles, int64_t kunits, int num_cus) {
-    const int64_t target = 4LL * num_cus;
-    int64_t S = (target + tiles - 1) / tiles;
-    const int64_t smax = kunits / 4 > 1 ? kunits / 4 : 1;
-    if (S > smax) S = smax;
+// Slices of the reduction dimension: the grid should fill every CU with as
+// many workgroups as fit at once (occupancy from the runtime) in one round,
+// since a second, partly filled round costs as much as a full one.
+int64_t pick_splits(int64_t tiles, int64_t kunits, int num_cus, int occ) {
+    const int64_t slots = (int64_t)num_cus * (occ > 0 ? occ : 1);
+    int64_t S = slots / tiles;
+    if (S > kunits) S = kunits;
     if (S < 1) S = 1;
     return S;
+}
+
+template <class K>
+int occupancy(K kernel) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(kernel),
+                                                     kThreads, 0) != hipSuccess || blocks < 1)
+        blocks = 1;
+    return blocks;
+}
+
+int right_sw() {
+    static const int v = [] {
+        const char* e = std::getenv("CNMF_RSW");
+        return (e && std::atoi(e) == 256) ? 256 : 128;
+    }();
+    return v;
+}
+
+int occ_right(int nt) {
+    static const int v16_128 = occupancy(k_sweep_right<16, 128, true, false, true>);
+    static const int v32_128 = occupancy(k_sweep_right<32, 128, true, false, true>);
+    static const int v16_256 = occupancy(k_sweep_right<16, 256, true, false, true>);
+    static const int v32_256 = occupancy(k_sweep_right<32, 256, true, false, true>);
+    if (right_sw() == 128) return nt == 16 ? v16_128 : v32_128;
+    return nt == 16 ? v16_256 : v32_256;
+}
+
+int occ_left() {
+    static const int v = occupancy(k_sweep_left<32, true>);
+    return v;
+}
+
+struct RightPlan { int64_t tiles, S, span; int nt, sw; };
+RightPlan right_plan(const Dev& d, int64_t R, int64_t C, int k) {
+    RightPlan p;
+    p.nt = k <= 16 ? 16 : 32;
+    p.sw = right_sw();
+    p.tiles = (R + 31) / 32;
+    const int64_t stages = (C + p.sw - 1) / p.sw;
+    p.S = pick_splits(p.tiles, stages, d.num_cus, occ_right(p.nt));
+    p.span = p.sw * ((stages + p.S - 1) / p.S);
+    p.S = (C + p.span - 1) / p.span;
+    return p;
+}
+
+struct LeftPlan { int64_t tiles, S, rspan; int nt; };
+LeftPlan left_plan(const Dev& d, int64_t R, int64_t C, int k) {
+    LeftPlan p;
+    p.nt = k <= 16 ? 16 : 32;
+    p.tiles = (C + 255) / 256;
+    const int64_t stages = (R + 15) / 16;
+    p.S = pick_splits(p.tiles, stages, d.num_cus, occ_left());
+    p.rspan = 16 * ((stages + p.S - 1) / p.S);
+    p.S = (R + p.rspan - 1) / p.rspan;
+    return p;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+hipError_t reduce(const Dev& d, int64_t rows, int k, int64_t S, int nt, const float* partial,
+                  float* out, int64_t ldo, bool trans) {
+    const int64_t tot = rows * nt;
+    hipLaunchKernelGGL(k_reduce_slices, dim3((unsigned)((tot + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, d.stream, rows, k, (int)S, nt, partial, out, ldo,
+                       trans ? 1 : 0);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 size_t sweep_right_partial_floats(const Dev& d, int64_t R, int64_t C) {
-    const int64_t tiles = (R + 31) / 32;
-    const int64_t S = pick_splits(tiles, (C + 31) / 32, d.num_cus);
+    const RightPlan p16 = right_plan(d, R, C, 16), p32 = right_plan(d, R, C, 32);
+    const int64_t S = p16.S > p32.S ? p16.S : p32.S;
     return S > 1 ? (size_t)(S * R * 32) : 0;
 }
 
-hipError_t sweep_right(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx,
-                       int k, const float* A, int64_t lda, bool a_trans, float* Y,
-                       int64_t ldy, float* partial) {
-    if (R <= 0 || k <= 0) return hipSuccess;
-    const int64_t tiles = (R + 31) / 32;
-    const int64_t nchunks = (C + 31) / 32;
-    const int64_t S = pick_splits(tiles, nchunks, d.num_cus);
-    const int64_t cps = (nchunks + S - 1) / S;
-    const bool vec = (ldx % 4 == 0) && aligned16(X) &&
-                     (!a_trans || ((lda % 4 == 0) && aligned16(A)));
-    dim3 grid((unsigned)tiles, (unsigned)S);
-    float* out = S > 1 ? partial : Y;
-    const int64_t ldo = S > 1 ? 32 : ldy;
-#define LAUNCH_R(AT, V, D) \
-    hipLaunchKernelGGL((k_sweep_right<AT, V, D>), grid, dim3(kThreads), 0, d.stream, R, C, X, \
-                       ldx, k, A, lda, out, ldo, cps)
-    if (S > 1) {
-        if (a_trans) { if (vec) LAUNCH_R(true, true, false); else LAUNCH_R(true, false, false); }
-        else { if (vec) LAUNCH_R(false, true, false); else LAUNCH_R(false, false, false); }
-    } else {
-        if (a_trans) { if (vec) LAUNCH_R(true, true, true); else LAUNCH_R(true, false, true); }
-        else { if (vec) LAUNCH_R(false, true, true); else LAUNCH_R(false, false, true); }
-    }
+hipError_t sweep_right(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx, int k,
+                       const float* A, int64_t lda, bool a_trans, float* Y, int64_t ldy,
+                       float* partial) {
+    if (R <= 0 || k <= 0 || C <= 0) return hipSuccess;
+    // 16-byte vector loads of X (and of A^T) need aligned rows.
+    const bool vec = ldx % 4 == 0 && aligned16(X) && (!a_trans || (lda % 4 == 0 && aligned16(A)));
+    const RightPlan p = right_plan(d, R, C, k);
+    dim3 grid((unsigned)p.tiles, (unsigned)p.S);
+    const bool direct = p.S == 1;
+    float* out = direct ? Y : partial;
+    const int64_t ldo = direct ? ldy : p.nt;
+#define LAUNCH_R(NT, SW, AT, D, V)                                                                  \
+    hipLaunchKernelGGL((k_sweep_right<NT, SW, AT, D, V>), grid, dim3(kThreads), 0, d.stream, R, C, \
+                       X, ldx, k, A, lda, out, ldo, p.span)
+#define LAUNCH_R2(NT, SW, AT, D) \
+    do { if (vec) LAUNCH_R(NT, SW, AT, D, true); else LAUNCH_R(NT, SW, AT, D, false); } while (0)
+#define LAUNCH_R3(NT, SW)                                                                         \
+    do {                                                                                          \
+        if (a_trans) { if (direct) LAUNCH_R2(NT, SW, true, true); else LAUNCH_R2(NT, SW, true, false); } \
+        else { if (direct) LAUNCH_R2(NT, SW, false, true); else LAUNCH_R2(NT, SW, false, false); }       \
+    } while (0)
+    if (p.nt == 16) { if (p.sw == 128) LAUNCH_R3(16, 128); else LAUNCH_R3(16, 256); }
+    else { if (p.sw == 128) LAUNCH_R3(32, 128); else LAUNCH_R3(32, 256); }
+#undef LAUNCH_R3
+#undef LAUNCH_R2
 #undef LAUNCH_R
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || S == 1) return e;
-    const int64_t tot = R * 32;
-    hipLaunchKernelGGL(k_reduce_slices, dim3((unsigned)((tot + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, d.stream, R, k, (int)S, partial, Y, ldy, 0);
-    return hipGetLastError();
+    if (e != hipSuccess || direct) return e;
+    return reduce(d, R, k, p.S, p.nt, partial, Y, ldy, false);
 }
 
 size_t sweep_left_partial_floats(const Dev& d, int64_t R, int64_t C) {
-    const int64_t tiles = (C + 127) / 128;
-    const int64_t S = pick_splits(tiles, (R + 15) / 16, d.num_cus);
-    return (size_t)(S * C * 32);
+    const LeftPlan p = left_plan(d, R, C, 32);
+    return (size_t)(p.S * C * 32);
 }
 
-hipError_t sweep_left(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx,
-                      int k, const float* B, int64_t ldb, float* Z, int64_t ldz, bool z_trans,
+hipError_t sweep_left(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx, int k,
+                      const float* B, int64_t ldb, float* Z, int64_t ldz, bool z_trans,
                       float* partial) {
-    if (C <= 0 || k <= 0) return hipSuccess;
-    const int64_t tiles = (C + 127) / 128;
-    const int64_t nblocks = (R + 15) / 16;
-    const int64_t S = pick_splits(tiles, nblocks, d.num_cus);
-    const int64_t bps = (nblocks + S - 1) / S;
-    const bool vec = (ldx % 4 == 0) && aligned16(X);
-    dim3 grid((unsigned)tiles, (unsigned)S);
-    if (vec)
-        hipLaunchKernelGGL(k_sweep_left<true>, grid, dim3(kThreads), 0, d.stream, R, C, X, ldx,
-                           k, B, ldb, partial, bps);
-    else
-        hipLaunchKernelGGL(k_sweep_left<false>, grid, dim3(kThreads), 0, d.stream, R, C, X,
-                           ldx, k, B, ldb, partial, bps);
+    if (C <= 0 || k <= 0 || R <= 0) return hipSuccess;
+    const bool vec = ldx % 4 == 0 && aligned16(X);
+    const LeftPlan p = left_plan(d, R, C, k);
+    dim3 grid((unsigned)p.tiles, (unsigned)p.S);
+#define LAUNCH_L(NT, V)                                                                          \
+    hipLaunchKernelGGL((k_sweep_left<NT, V>), grid, dim3(kThreads), 0, d.stream, R, C, X, ldx, k, \
+                       B, ldb, partial, p.rspan)
+    if (p.nt == 16) { if (vec) LAUNCH_L(16, true); else LAUNCH_L(16, false); }
+    else { if (vec) LAUNCH_L(32, true); else LAUNCH_L(32, false); }
+#undef LAUNCH_L
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t tot = C * 32;
-    hipLaunchKernelGGL(k_reduce_slices, dim3((unsigned)((tot + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, d.stream, C, k, (int)S, partial, Z, ldz,
-                       z_trans ? 1 : 0);
-    return hipGetLastError();
+    return reduce(d, C, k, p.S, p.nt, partial, Z, ldz, z_trans);
 }
 
 // ---------------------------------------------------------------------------
