@@ -17,6 +17,7 @@ struct cnmf_ctx {
     Dev dev;
     Control* ctl = nullptr;       // device
     uint64_t* slots = nullptr;    // device, tagged exchange words of the phase kernels
+    uint64_t* oxch = nullptr;     // device, tagged exchange words of the orthonormalisation
     unsigned seq = 0;             // last tag used
     int dlag = 2;                 // steps between a norm and its stopping test
     char* ws = nullptr;           // device workspace
@@ -33,6 +34,8 @@ int from_hip(hipError_t e) { return e == hipSuccess ? CNMF_OK : CNMF_EHIP; }
 hipError_t next_seq(cnmf_ctx* c, unsigned* seq) {
     if (++c->seq >= (1u << 22)) {
         hipError_t e = fill_u64(c->dev, c->slots, (int64_t)kSlotWords, 0);
+        if (e != hipSuccess) return e;
+        e = fill_u64(c->dev, c->oxch, (int64_t)orth_exchange_words(), 0);
         if (e != hipSuccess) return e;
         c->seq = 1;
     }
@@ -155,16 +158,20 @@ int cnmf_create(cnmf_ctx** out, int device, void* stream) {
         delete c;
         return CNMF_ENOMEM;
     }
-    if (hipMalloc((void**)&c->slots, kSlotWords * sizeof(uint64_t)) != hipSuccess) {
+    if (hipMalloc((void**)&c->slots, kSlotWords * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc((void**)&c->oxch, orth_exchange_words() * sizeof(uint64_t)) != hipSuccess) {
         (void)hipFree(c->ctl);
+        if (c->slots) (void)hipFree(c->slots);
         delete c;
         return CNMF_ENOMEM;
     }
     if (hipMemset(c->ctl, 0, sizeof(Control)) != hipSuccess ||
         hipMemset(c->slots, 0, kSlotWords * sizeof(uint64_t)) != hipSuccess ||
+        hipMemset(c->oxch, 0, orth_exchange_words() * sizeof(uint64_t)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(c->ctl);
         (void)hipFree(c->slots);
+        (void)hipFree(c->oxch);
         delete c;
         return CNMF_EHIP;
     }
@@ -183,6 +190,7 @@ int cnmf_destroy(cnmf_ctx* c) {
     if (c->ws) (void)hipFree(c->ws);
     if (c->ctl) (void)hipFree(c->ctl);
     if (c->slots) (void)hipFree(c->slots);
+    if (c->oxch) (void)hipFree(c->oxch);
     delete c;
     return CNMF_OK;
 }
@@ -268,13 +276,11 @@ int cnmf_orth(cnmf_ctx* c, int64_t N, int32_t l, const float* Y, const float* po
     if (!c || N < 1 || l < 1 || l > 32 || l > N) return CNMF_EINVAL;
     if (bad_ptr(Y) || bad_ptr(pool) || bad_ptr(Q)) return CNMF_EINVAL;
     if (!(tau2 > 0.0 && tau2 < 1.0)) return CNMF_EINVAL;
-    Arena a;
-    size_t off = a.take<double>(orth_workspace_doubles(c->dev, N, l));
-    int rc = ensure_ws(c, a.off);
-    if (rc) return rc;
     if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
-    return from_hip(orth(c->dev, N, l, Y, pool, pool_trans != 0, tau2, Q, replaced,
-                         at<double>(c, off), c->ctl));
+    unsigned seq = 0;
+    CK(next_seq(c, &seq));
+    return from_hip(orth(c->dev, N, l, Y, pool, pool_trans != 0, tau2, Q, nullptr, 0, replaced,
+                         c->oxch, seq, c->ctl));
 }
 
 int cnmf_lipschitz(cnmf_ctx* c, int32_t p, const float* W, double* out) {
@@ -326,20 +332,22 @@ static int rsi_impl(cnmf_ctx* c, int64_t n, int64_t m, const float* X, const uin
                     float* QL_out, float* QR_out, float* XL_out, float* XR_out) {
     const int l = prm->p + prm->nu;
     const bool bf = Xb != nullptr;
+    const int64_t ldt = (m + 3) / 4 * 4;       // pitch of the transposed m-space panels
     Arena a;
     const size_t o_oRt = a.take<float>((size_t)n * l);
     const size_t o_Yn = a.take<float>((size_t)n * l);
     const size_t o_QL = a.take<float>((size_t)n * l);
     const size_t o_Ym = a.take<float>((size_t)m * l);
     const size_t o_QRt = a.take<float>((size_t)m * l);
+    const size_t o_oLT = a.take<float>((size_t)l * ldt);
+    const size_t o_QRtT = a.take<float>((size_t)l * ldt);
+    const size_t o_QLtT = a.take<float>((size_t)l * ldt);
     size_t part = std::max(sweep_right_partial_floats(c->dev, n, m),
                            sweep_left_partial_floats(c->dev, n, m));
     if (bf)
         part = std::max(part, std::max(sweep_right_bf16_partial_floats(c->dev, n, m),
                                        sweep_left_bf16_partial_floats(c->dev, n, m)));
     const size_t o_part = a.take<float>(part);
-    const size_t o_orth = a.take<double>(std::max(orth_workspace_doubles(c->dev, n, l),
-                                                  orth_workspace_doubles(c->dev, m, l)));
     const size_t o_pk = a.take<uint16_t>(bf ? (size_t)std::max(n, m) * 32 * 2 : 1);
     int rc = ensure_ws(c, a.off);
     if (rc) return rc;
@@ -350,41 +358,59 @@ static int rsi_impl(cnmf_ctx* c, int64_t n, int64_t m, const float* X, const uin
     float* QL = at<float>(c, o_QL);
     float* Ym = at<float>(c, o_Ym);
     float* QRt = at<float>(c, o_QRt);
+    float* oLT = at<float>(c, o_oLT);
+    float* QRtT = at<float>(c, o_QRtT);
+    float* QLtT = at<float>(c, o_QLtT);
     float* pt = at<float>(c, o_part);
-    double* ows = at<double>(c, o_orth);
     uint16_t* pk = at<uint16_t>(c, o_pk);
     const double tau2 = prm->tau2;
 
-    auto right = [&](const float* A, float* Y) -> hipError_t {   // Y (n x l) = X A, A m x l
-        if (bf) return sweep_right_bf16(d, n, m, Xb, ldx, l, A, l, Y, l, pt, pk);
-        return sweep_right(d, n, m, X, ldx, l, A, l, false, Y, l, pt);
+    // Y (n x l) = X A with A (m x l) given as its transpose AT (l x ldt)
+    auto right = [&](const float* AT, float* Y) -> hipError_t {
+        if (bf) return sweep_right_bf16(d, n, m, Xb, ldx, l, AT, ldt, Y, l, pt, pk);
+        return sweep_right(d, n, m, X, ldx, l, AT, ldt, true, Y, l, pt);
     };
     auto left = [&](const float* B, float* Z, bool trans) -> hipError_t {  // Z = X^T B
         const int64_t ldz = trans ? m : l;
         if (bf) return sweep_left_bf16(d, n, m, Xb, ldx, l, B, l, Z, ldz, trans, pt, pk);
         return sweep_left(d, n, m, X, ldx, l, B, l, Z, ldz, trans, pt);
     };
+    // orthonormal basis of Y (N x l) into Q, pool: Omega_R^T (n-space) or
+    // Omega_L (m-space); QT: optional transposed copy (l x ldt)
+    auto orth_n = [&](const float* Y, float* Q) -> hipError_t {
+        unsigned seq = 0;
+        hipError_t e = next_seq(c, &seq);
+        if (e != hipSuccess) return e;
+        return orth(d, n, l, Y, oRt, false, tau2, Q, nullptr, 0, nullptr, c->oxch, seq, c->ctl);
+    };
+    auto orth_m = [&](const float* Y, float* Q, float* QT) -> hipError_t {
+        unsigned seq = 0;
+        hipError_t e = next_seq(c, &seq);
+        if (e != hipSuccess) return e;
+        return orth(d, m, l, Y, oL, false, tau2, Q, QT, ldt, nullptr, c->oxch, seq, c->ctl);
+    };
 
     if (!bf && (prm->flags & CNMF_FLAG_VALIDATE_INPUT)) CK(check_input(d, n, m, X, ldx, c->ctl));
     CK(transpose(d, l, n, oR, n, oRt, l));                       // Omega_R^T, n x l
+    CK(transpose(d, m, l, oL, l, oLT, ldt));                     // Omega_L^T, l x m
     // Step 0: sketches X Omega_L and (Omega_R X)^T and their bases.
-    CK(right(oL, Yn));
-    CK(orth(d, n, l, Yn, oRt, false, tau2, QL, nullptr, ows, c->ctl));
+    CK(right(oLT, Yn));
+    CK(orth_n(Yn, QL));
     CK(left(oRt, Ym, false));
-    CK(orth(d, m, l, Ym, oL, false, tau2, QRt, nullptr, ows, c->ctl));
+    CK(orth_m(Ym, QRt, QRtT));
     for (int k = 1; k <= prm->q; ++k) {
         // Q~_L^(k) = orth(X^T Q_L^(k-1)), kept in the Q_R output (m x l).
         CK(left(QL, Ym, false));
-        CK(orth(d, m, l, Ym, oL, false, tau2, QR_out, nullptr, ows, c->ctl));
+        CK(orth_m(Ym, QR_out, QLtT));
         // Q~_R^(k)^T = orth(X Q_R^(k-1)^T), kept in the Q_L output (n x l).
-        CK(right(QRt, Yn));
-        CK(orth(d, n, l, Yn, oRt, false, tau2, QL_out, nullptr, ows, c->ctl));
+        CK(right(QRtT, Yn));
+        CK(orth_n(Yn, QL_out));
         // X Q~_L^(k) (n x l) and (Q~_R^(k) X)^T (m x l).
-        CK(right(QR_out, XR_out));
+        CK(right(QLtT, XR_out));
         if (k < prm->q) {
             CK(left(QL_out, Ym, false));
-            CK(orth(d, n, l, XR_out, oRt, false, tau2, QL, nullptr, ows, c->ctl));
-            CK(orth(d, m, l, Ym, oL, false, tau2, QRt, nullptr, ows, c->ctl));
+            CK(orth_n(XR_out, QL));
+            CK(orth_m(Ym, QRt, QRtT));
         } else {
             CK(left(QL_out, XL_out, true));   // X_L = Q_L^T X, l x m
         }

@@ -74,24 +74,58 @@ __device__ __forceinline__ bool grid_sync(Control* ctl, unsigned nblocks) {
     return s_ok != 0;
 }
 
-// Wavefront sum (64 lanes) in FP64, fixed butterfly order: every lane ends
-// with the same value, bit-identical across runs.
+// Wavefront reductions with DPP row operations (no LDS traffic): xor 1 and
+// xor 2 inside quads, rotations by 4 and 8 inside 16-lane rows, then the four
+// row results combined in a fixed order.  Every lane gets the same value and
+// the result is bit-identical across runs and across workgroups.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppXor1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int kDppRor4 = 0x124;    // row_ror:4
+constexpr int kDppRor8 = 0x128;    // row_ror:8
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v += dpp_d<kDppXor1>(v);
+    v += dpp_d<kDppXor2>(v);
+    v += dpp_d<kDppRor4>(v);
+    v += dpp_d<kDppRor8>(v);
+    return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v += dpp_f<kDppXor1>(v);
+    v += dpp_f<kDppXor2>(v);
+    v += dpp_f<kDppRor4>(v);
+    v += dpp_f<kDppRor8>(v);
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (a + b) + (c + d);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
-    return v;
+    v = fmax(v, dpp_d<kDppXor1>(v));
+    v = fmax(v, dpp_d<kDppXor2>(v));
+    v = fmax(v, dpp_d<kDppRor4>(v));
+    v = fmax(v, dpp_d<kDppRor8>(v));
+    return fmax(fmax(lane_d(v, 0), lane_d(v, 16)), fmax(lane_d(v, 32), lane_d(v, 48)));
 }
 
 // ---------------------------------------------------------------------------
@@ -128,11 +162,13 @@ hipError_t transpose(const Dev& d, int64_t R, int64_t C, const float* A, int64_t
 hipError_t check_input(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx,
                        Control* ctl);
 
-// orth.hip: workspace in doubles for an N x l panel
-size_t orth_workspace_doubles(const Dev& d, int64_t N, int l);
+// orth.hip: CholeskyQR2 with the rank rule in one launch.  xch: exchange
+// words (orth_exchange_words()); seq: launch tag (< 2^22), fresh per call.
+// QT (optional): transposed copy of Q with row pitch ldqt.
+size_t orth_exchange_words();
 hipError_t orth(const Dev& d, int64_t N, int l, const float* Y, const float* pool,
-                bool pool_trans, double tau2, float* Q, int32_t* replaced, double* ws,
-                Control* ctl);
+                bool pool_trans, double tau2, float* Q, float* QT, int64_t ldqt,
+                int32_t* replaced, uint64_t* xch, unsigned seq, Control* ctl);
 
 // small.hip
 hipError_t lipschitz(const Dev& d, int p, const float* W, double* out, Control* ctl);

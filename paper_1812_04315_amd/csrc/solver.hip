@@ -77,24 +77,27 @@ __device__ double lambda_max_wave(double (*A)[33], int p, double* v, double* wv,
         const double xi = in ? A[i][k] : 0.0;
         const double sigma = wave_sum(xi * xi);
         const double x0 = A[k + 1][k];
+        const double akk = A[k][k];
         if (sigma == 0.0) {
-            if (lane == 0) { dg[k] = A[k][k]; eo[k] = 0.0; }
+            if (lane == 0) { dg[k] = akk; eo[k] = 0.0; }
             continue;
         }
         const double alpha = -copysign(sqrt(sigma), x0);
         const double v0 = x0 - alpha;
-        const double vn = sqrt(sigma - x0 * x0 + v0 * v0);
-        if (in) v[i] = ((i == k + 1) ? v0 : xi) / vn;
+        const double inv = 1.0 / sqrt(sigma - x0 * x0 + v0 * v0);
+        const double vi = in ? ((i == k + 1) ? v0 : xi) * inv : 0.0;
+        if (in) v[i] = vi;
         __builtin_amdgcn_wave_barrier();
         double ui = 0.0;
         if (in)
             for (int j = k + 1; j < p; ++j) ui = fma(A[i][j], v[j], ui);
-        const double c = wave_sum(in ? v[i] * ui : 0.0);
-        if (in) wv[i] = 2.0 * ui - 2.0 * c * v[i];
+        const double c = wave_sum(vi * ui);
+        const double wi = 2.0 * (ui - c * vi);
+        if (in) wv[i] = wi;
         __builtin_amdgcn_wave_barrier();
         if (in)
-            for (int j = k + 1; j < p; ++j) A[i][j] -= v[i] * wv[j] + wv[i] * v[j];
-        if (lane == 0) { dg[k] = A[k][k]; eo[k] = alpha; }
+            for (int j = k + 1; j < p; ++j) A[i][j] -= vi * wv[j] + wi * v[j];
+        if (lane == 0) { dg[k] = akk; eo[k] = alpha; }
         __builtin_amdgcn_wave_barrier();
     }
     if (lane == 0) {
@@ -105,23 +108,23 @@ __device__ double lambda_max_wave(double (*A)[33], int p, double* v, double* wv,
         dg[p - 1] = A[p - 1][p - 1];
     }
     __builtin_amdgcn_wave_barrier();
-    double lo = -INFINITY, hi = -INFINITY;
-    bool bad = false;
-    for (int i = 0; i < p; ++i) {
-        const double el = (i > 0) ? fabs(eo[i - 1]) : 0.0;
-        const double er = (i + 1 < p) ? fabs(eo[i]) : 0.0;
-        lo = fmax(lo, dg[i]);
-        hi = fmax(hi, dg[i] + el + er);
-        if (!isfinite(dg[i]) || !isfinite(er)) bad = true;
-    }
+    // Bracket [lo, hi] around lambda_max: the largest diagonal entry and the
+    // Gershgorin bound.  Lane i < p holds row i of the tridiagonal matrix.
+    const double di = lane < p ? dg[lane] : -INFINITY;
+    const double el = (lane > 0 && lane < p) ? fabs(eo[lane - 1]) : 0.0;
+    const double er = (lane + 1 < p) ? fabs(eo[lane]) : 0.0;
+    const double lo = wave_max(di);
+    const double hi = wave_max(lane < p ? di + el + er : -INFINITY);
+    const int bad = __any(lane < p && (!isfinite(di) || !isfinite(er)));
     if (bad) return NAN;
     if (!(hi > 0.0)) return fmax(lo, 0.0);
-    // Scale to [.., 1] so the pivots stay O(1).
+    // Scale to [.., 1] so the pivots stay O(1), then multisection: 64 Sturm
+    // counts per round narrow the bracket 65-fold.
     const double sc = 1.0 / hi;
     double l0 = lo * sc, h0 = 1.0;
     const double pivmin = 1e-300;
-    for (int round = 0; round < 12 && h0 > l0; ++round) {
-        const double x = l0 + (h0 - l0) * (double)(lane + 1) / 65.0;
+    for (int round = 0; round < 9 && h0 > l0; ++round) {
+        const double x = l0 + (h0 - l0) * (double)(lane + 1) * (1.0 / 65.0);
         int cnt = 0;   // eigenvalues of T/hi below x (negative LDL^T pivots)
         double q = dg[0] * sc - x;
         if (fabs(q) < pivmin) q = -pivmin;
@@ -139,10 +142,10 @@ __device__ double lambda_max_wave(double (*A)[33], int p, double* v, double* wv,
         double nlo = l0, nhi = h0;
         if (mask) {
             const int first = __ffsll((long long)mask) - 1;
-            nhi = __shfl(x, first, 64);
-            if (first > 0) nlo = __shfl(x, first - 1, 64);
+            nhi = lane_d(x, first);
+            if (first > 0) nlo = lane_d(x, first - 1);
         } else {
-            nlo = __shfl(x, 63, 64);
+            nlo = lane_d(x, 63);
         }
         if (!(nhi - nlo < h0 - l0)) break;
         l0 = nlo;
