@@ -132,8 +132,12 @@ int cnmf_rsi(cnmf_ctx* ctx, int64_t n, int64_t m, const float* X, int64_t ldx,
              float* Q_L, float* Q_R, float* X_L, float* X_R);
 
 /* Same, with the X-sized sweeps in BF16 on MFMA (FP32 accumulation):
- *   Xb  n x m (ldxb) bfloat16 bit patterns of X (see cnmf_to_bf16).
- * Gram, Cholesky and outputs as cnmf_rsi; X_L, X_R are computed from Xb. */
+ *   Xb  n x m (ldxb >= m, any alignment) bfloat16 bit patterns of X (see
+ *       cnmf_to_bf16).
+ * Every X product takes its skinny operand (Omega, then the current basis)
+ * rounded to bfloat16; the orthonormalisation (FP64 Gram and Cholesky, FP32
+ * apply) and the outputs are as in cnmf_rsi; X_L, X_R are products with Xb.
+ * sweep_prec is ignored. */
 int cnmf_rsi_bf16(cnmf_ctx* ctx, int64_t n, int64_t m, const uint16_t* Xb,
                   int64_t ldxb, const cnmf_params* prm, const float* omega_L,
                   const float* omega_R, float* Q_L, float* Q_R, float* X_L,
@@ -180,6 +184,19 @@ int cnmf_sweep_right(cnmf_ctx* ctx, int64_t R, int64_t C, const float* X,
 int cnmf_sweep_left(cnmf_ctx* ctx, int64_t R, int64_t C, const float* X,
                     int64_t ldx, int32_t k, const float* B, int64_t ldb,
                     float* Z, int64_t ldz, int32_t z_trans);
+
+/* BF16 form of the two sweeps (the precision form of the X-sized products
+ * of Algorithm 2): Xb holds X as bfloat16 bit patterns (R x C, row pitch
+ * ldxb >= C, any alignment); the skinny operand is rounded to bfloat16
+ * (nearest even) inside the call; products on the matrix cores with FP32
+ * accumulation.  Arguments and outputs otherwise as cnmf_sweep_right /
+ * cnmf_sweep_left; R, C >= 1, 1 <= k <= 32. */
+int cnmf_sweep_right_bf16(cnmf_ctx* ctx, int64_t R, int64_t C, const uint16_t* Xb,
+                          int64_t ldxb, int32_t k, const float* A, int64_t lda,
+                          int32_t a_trans, float* Y, int64_t ldy);
+int cnmf_sweep_left_bf16(cnmf_ctx* ctx, int64_t R, int64_t C, const uint16_t* Xb,
+                         int64_t ldxb, int32_t k, const float* B, int64_t ldb,
+                         float* Z, int64_t ldz, int32_t z_trans);
 
 /* Orthonormal basis of Y (N x l, ld = l) by CholeskyQR2 with the rank rule
  * of cnmf_rsi; pool is N x l (pool_trans = 0, ld = l) or l x N

@@ -8,4 +8,5 @@ from .nenmf import (  # noqa: F401
     alpha_series, momentum_weights, orth, rsi, lipschitz, gradient,
     projected_gradient, pg_norm, nesterov_nnls, g_data_plain, f_data_plain,
     g_data_compressed, f_data_compressed, nenmf, rre, svd_floor,
+    bf16_bits, bf16_value, bf16_round,
 )

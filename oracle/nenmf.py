@@ -118,6 +118,34 @@ def orth(Y, pool, tau2: float = 1e-9):
     return Q, replaced
 
 
+# ---------------------------------------------------------------------------
+# bfloat16 rounding for the precision form (round to nearest, ties to even)
+# ---------------------------------------------------------------------------
+
+def bf16_bits(x) -> np.ndarray:
+    """bfloat16 bit patterns of FP32 values: keep the upper 16 bits after
+    rounding the lower 16 to nearest, ties to even; NaN stays a quiet NaN."""
+    u = np.ascontiguousarray(np.asarray(x, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    is_nan = ((u & 0x7F800000) == 0x7F800000) & ((u & 0x007FFFFF) != 0)
+    half = 0x7FFF + ((u >> 16) & 1)
+    r = ((u + half) >> 16) & 0xFFFF
+    r = np.where(is_nan, (u >> 16) | 0x40, r)
+    return r.astype(np.uint16)
+
+
+def bf16_value(bits) -> np.ndarray:
+    """FP64 values of bfloat16 bit patterns (exact)."""
+    b = np.asarray(bits, dtype=np.uint16).astype(np.uint32) << 16
+    with np.errstate(invalid="ignore"):
+        return b.view(np.float32).astype(F64)
+
+
+def bf16_round(x) -> np.ndarray:
+    """Round FP32 (or FP64, first rounded to FP32) values to bfloat16,
+    returned as FP64."""
+    return bf16_value(bf16_bits(np.asarray(x, dtype=np.float32)))
+
+
 @dataclass
 class RSIResult:
     Q_L: np.ndarray   # n x l, orthonormal columns (left basis: X_L = Q_L^T X)
@@ -127,7 +155,7 @@ class RSIResult:
     replaced: list = field(default_factory=list)  # (stage, bool array) per orth
 
 
-def rsi(X, omega_L, omega_R, q: int, tau2: float = 1e-9) -> RSIResult:
+def rsi(X, omega_L, omega_R, q: int, tau2: float = 1e-9, bf16: bool = False) -> RSIResult:
     """Randomized subspace iteration, Sec. 3, Algorithm 2, in FP64.
 
     Readings: the two sketches X Omega_L and Omega_R X start two independent
@@ -141,13 +169,24 @@ def rsi(X, omega_L, omega_R, q: int, tau2: float = 1e-9) -> RSIResult:
 
     Replacement pools: n-space panels take columns of Omega_R^T, m-space
     panels take columns of Omega_L.
+
+    bf16=True emulates the precision form: X and, before every product with
+    X, the skinny operand are rounded to bfloat16; the products and all the
+    rest stay FP64.
     """
     if q < 1:
         raise ValueError("q >= 1 required")
-    X = np.asarray(X, dtype=F64)
+    X = bf16_round(X) if bf16 else np.asarray(X, dtype=F64)
     oL = np.asarray(omega_L, dtype=F64)       # m x l
     oRt = np.asarray(omega_R, dtype=F64).T    # n x l
     reps = []
+    rnd = bf16_round if bf16 else (lambda a: a)
+
+    def right(P):                             # X P
+        return X @ rnd(P)
+
+    def left(P):                              # X^T P
+        return X.T @ rnd(P)
 
     def orth_n(Y, tag):
         Q, r = orth(Y, oRt, tau2)
@@ -160,14 +199,14 @@ def rsi(X, omega_L, omega_R, q: int, tau2: float = 1e-9) -> RSIResult:
         return Q
 
     # Sketches of step 0 and their bases.
-    QL = orth_n(X @ oL, "L0")          # basis of X Omega_L           (n x l)
-    QRt = orth_m(X.T @ oRt, "R0")      # basis of (Omega_R X)^T       (m x l)
+    QL = orth_n(right(oL), "L0")       # basis of X Omega_L           (n x l)
+    QRt = orth_m(left(oRt), "R0")      # basis of (Omega_R X)^T       (m x l)
     A = B = Qt_L = Qt_Rt = None
     for k in range(1, q + 1):
-        Qt_L = orth_m(X.T @ QL, f"Lt{k}")      # X^T Q_L^(k-1)          (m x l)
-        Qt_Rt = orth_n(X @ QRt, f"Rt{k}")      # (Q_R^(k-1) X^T)^T      (n x l)
-        A = X @ Qt_L                           # X Q~_L^(k)             (n x l)
-        B = X.T @ Qt_Rt                        # (Q~_R^(k) X)^T         (m x l)
+        Qt_L = orth_m(left(QL), f"Lt{k}")      # X^T Q_L^(k-1)          (m x l)
+        Qt_Rt = orth_n(right(QRt), f"Rt{k}")   # (Q_R^(k-1) X^T)^T      (n x l)
+        A = right(Qt_L)                        # X Q~_L^(k)             (n x l)
+        B = left(Qt_Rt)                        # (Q~_R^(k) X)^T         (m x l)
         if k < q:
             QL = orth_n(A, f"L{k}")
             QRt = orth_m(B, f"R{k}")

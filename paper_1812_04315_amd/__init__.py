@@ -30,6 +30,7 @@ EXPORTED = [
     "cnmf_params_default", "cnmf_strerror", "cnmf_create", "cnmf_destroy",
     "cnmf_set_stream", "cnmf_clock_hz", "cnmf_status", "cnmf_rsi", "cnmf_rsi_bf16",
     "cnmf_to_bf16", "cnmf_solve", "cnmf_rre", "cnmf_sweep_right", "cnmf_sweep_left",
+    "cnmf_sweep_right_bf16", "cnmf_sweep_left_bf16",
     "cnmf_orth", "cnmf_lipschitz", "cnmf_nnls",
 ]
 
@@ -86,6 +87,8 @@ def lib() -> ctypes.CDLL:
             "cnmf_rre": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, P, I64, I32, P]),
             "cnmf_sweep_right": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, I32, P, I64]),
             "cnmf_sweep_left": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, P, I64, I32]),
+            "cnmf_sweep_right_bf16": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, I32, P, I64]),
+            "cnmf_sweep_left_bf16": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, P, I64, I32]),
             "cnmf_orth": (ctypes.c_int, [P, I64, I32, P, P, I32, D, P, P]),
             "cnmf_lipschitz": (ctypes.c_int, [P, I32, P, P]),
             "cnmf_nnls": (ctypes.c_int, [P, I64, I32, P, I64, I64, P, P, D, I32, I32, I32, P, P, P]),
@@ -367,6 +370,38 @@ def sweep_left(X, B, z_trans: bool = False, out=None):
         if out is None else out
     _call("cnmf_sweep_left", context().h, R, C, _ptr(X), _ld(X), k, _ptr(B), _ld(B), _ptr(Z),
           _ld(Z), 1 if z_trans else 0)
+    return Z
+
+
+def sweep_right_bf16(Xb, A, a_trans: bool = False, out=None):
+    """Y = X A on the matrix cores in BF16: Xb holds bfloat16 bit patterns
+    (int16), A (C x k, or k x C if a_trans) is rounded to bfloat16."""
+    torch = _torch()
+    _need(Xb, torch.int16, "Xb", ld_ok=True)
+    _need(A, torch.float32, "A", ld_ok=True)
+    R, C = Xb.shape
+    k = A.shape[0] if a_trans else A.shape[1]
+    if (A.shape[1] if a_trans else A.shape[0]) != C:
+        raise ValueError("inner dimensions differ")
+    Y = torch.empty(R, k, device=Xb.device) if out is None else out
+    _call("cnmf_sweep_right_bf16", context().h, R, C, _ptr(Xb), _ld(Xb), k, _ptr(A), _ld(A),
+          1 if a_trans else 0, _ptr(Y), _ld(Y))
+    return Y
+
+
+def sweep_left_bf16(Xb, B, z_trans: bool = False, out=None):
+    """Z = X^T B on the matrix cores in BF16 (B rounded to bfloat16)."""
+    torch = _torch()
+    _need(Xb, torch.int16, "Xb", ld_ok=True)
+    _need(B, torch.float32, "B", ld_ok=True)
+    R, C = Xb.shape
+    k = B.shape[1]
+    if B.shape[0] != R:
+        raise ValueError("inner dimensions differ")
+    Z = (torch.empty(k, C, device=Xb.device) if z_trans else torch.empty(C, k, device=Xb.device)) \
+        if out is None else out
+    _call("cnmf_sweep_left_bf16", context().h, R, C, _ptr(Xb), _ld(Xb), k, _ptr(B), _ld(B),
+          _ptr(Z), _ld(Z), 1 if z_trans else 0)
     return Z
 
 

@@ -271,6 +271,37 @@ int cnmf_sweep_left(cnmf_ctx* c, int64_t R, int64_t C, const float* X, int64_t l
                                at<float>(c, off)));
 }
 
+int cnmf_sweep_right_bf16(cnmf_ctx* c, int64_t R, int64_t C, const uint16_t* Xb, int64_t ldxb,
+                          int32_t k, const float* A, int64_t lda, int32_t a_trans, float* Y,
+                          int64_t ldy) {
+    if (!c || R < 1 || C < 1 || k < 1 || k > 32) return CNMF_EINVAL;
+    if (bad_ptr(Xb) || bad_ptr(A) || bad_ptr(Y) || ldxb < C || ldy < k) return CNMF_EINVAL;
+    if (a_trans ? lda < C : lda < k) return CNMF_EINVAL;
+    Arena a;
+    const size_t off = a.take<float>(sweep_right_bf16_partial_floats(c->dev, R, C));
+    const size_t opk = a.take<uint16_t>(bf16_pack_elems(C));
+    int rc = ensure_ws(c, a.off);
+    if (rc) return rc;
+    if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
+    return from_hip(sweep_right_bf16(c->dev, R, C, Xb, ldxb, k, A, lda, a_trans != 0, Y, ldy,
+                                     at<float>(c, off), at<uint16_t>(c, opk)));
+}
+
+int cnmf_sweep_left_bf16(cnmf_ctx* c, int64_t R, int64_t C, const uint16_t* Xb, int64_t ldxb,
+                         int32_t k, const float* B, int64_t ldb, float* Z, int64_t ldz,
+                         int32_t z_trans) {
+    if (!c || R < 1 || C < 1 || k < 1 || k > 32) return CNMF_EINVAL;
+    if (bad_ptr(Xb) || bad_ptr(B) || bad_ptr(Z) || ldxb < C || ldb < k) return CNMF_EINVAL;
+    if (z_trans ? ldz < C : ldz < k) return CNMF_EINVAL;
+    Arena a;
+    const size_t off = a.take<float>(sweep_left_bf16_partial_floats(c->dev, R, C));
+    int rc = ensure_ws(c, a.off);
+    if (rc) return rc;
+    if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
+    return from_hip(sweep_left_bf16(c->dev, R, C, Xb, ldxb, k, B, ldb, Z, ldz, z_trans != 0,
+                                    at<float>(c, off)));
+}
+
 int cnmf_orth(cnmf_ctx* c, int64_t N, int32_t l, const float* Y, const float* pool,
               int32_t pool_trans, double tau2, float* Q, int32_t* replaced) {
     if (!c || N < 1 || l < 1 || l > 32 || l > N) return CNMF_EINVAL;
@@ -348,7 +379,7 @@ static int rsi_impl(cnmf_ctx* c, int64_t n, int64_t m, const float* X, const uin
         part = std::max(part, std::max(sweep_right_bf16_partial_floats(c->dev, n, m),
                                        sweep_left_bf16_partial_floats(c->dev, n, m)));
     const size_t o_part = a.take<float>(part);
-    const size_t o_pk = a.take<uint16_t>(bf ? (size_t)std::max(n, m) * 32 * 2 : 1);
+    const size_t o_pk = a.take<uint16_t>(bf ? bf16_pack_elems(m) : 1);
     int rc = ensure_ws(c, a.off);
     if (rc) return rc;
     if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
@@ -367,12 +398,12 @@ static int rsi_impl(cnmf_ctx* c, int64_t n, int64_t m, const float* X, const uin
 
     // Y (n x l) = X A with A (m x l) given as its transpose AT (l x ldt)
     auto right = [&](const float* AT, float* Y) -> hipError_t {
-        if (bf) return sweep_right_bf16(d, n, m, Xb, ldx, l, AT, ldt, Y, l, pt, pk);
+        if (bf) return sweep_right_bf16(d, n, m, Xb, ldx, l, AT, ldt, true, Y, l, pt, pk);
         return sweep_right(d, n, m, X, ldx, l, AT, ldt, true, Y, l, pt);
     };
     auto left = [&](const float* B, float* Z, bool trans) -> hipError_t {  // Z = X^T B
         const int64_t ldz = trans ? m : l;
-        if (bf) return sweep_left_bf16(d, n, m, Xb, ldx, l, B, l, Z, ldz, trans, pt, pk);
+        if (bf) return sweep_left_bf16(d, n, m, Xb, ldx, l, B, l, Z, ldz, trans, pt);
         return sweep_left(d, n, m, X, ldx, l, B, l, Z, ldz, trans, pt);
     };
     // orthonormal basis of Y (N x l) into Q, pool: Omega_R^T (n-space) or
@@ -436,8 +467,7 @@ int cnmf_rsi_bf16(cnmf_ctx* c, int64_t n, int64_t m, const uint16_t* Xb, int64_t
     if (!c || n < 1 || m < 1) return CNMF_EINVAL;
     int rc = check_params(prm, n, m, true);
     if (rc) return rc;
-    if (bad_ptr(Xb) || ldxb < m || (ldxb % 8) != 0 || (reinterpret_cast<uintptr_t>(Xb) & 15u))
-        return CNMF_EINVAL;
+    if (bad_ptr(Xb) || ldxb < m) return CNMF_EINVAL;
     if (bad_ptr(omega_L) || bad_ptr(omega_R)) return CNMF_EINVAL;
     if (bad_ptr(Q_L) || bad_ptr(Q_R) || bad_ptr(X_L) || bad_ptr(X_R)) return CNMF_EINVAL;
     return rsi_impl(c, n, m, nullptr, Xb, ldxb, prm, omega_L, omega_R, Q_L, Q_R, X_L, X_R);

@@ -128,6 +128,15 @@ __device__ __forceinline__ double wave_max(double v) {
     return fmax(fmax(lane_d(v, 0), lane_d(v, 16)), fmax(lane_d(v, 32), lane_d(v, 48)));
 }
 
+// FP32 -> bfloat16 bits, round to nearest even; NaN stays NaN (quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch helpers (defined in the .hip files, called by api.cpp).
 // All return hipSuccess or the launch error.
@@ -147,14 +156,32 @@ size_t sweep_left_partial_floats(const Dev& d, int64_t R, int64_t C);
 hipError_t sweep_left(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx,
                       int k, const float* B, int64_t ldb, float* Z, int64_t ldz,
                       bool z_trans, float* partial);
+// reduce_slices: out (rows x k, or k x rows if trans) = sum of S partial
+// slices [S][rows][nt] in slice order (bitwise reproducible).
+hipError_t reduce_slices(const Dev& d, int64_t rows, int k, int64_t S, int nt,
+                         const float* partial, float* out, int64_t ldo, bool trans);
+// Workgroups per slice so that one round of the grid fills every CU.
+inline int64_t pick_splits(int64_t tiles, int64_t kunits, int num_cus, int occ) {
+    const int64_t slots = (int64_t)num_cus * (occ > 0 ? occ : 1);
+    int64_t S = slots / tiles;
+    if (S > kunits) S = kunits;
+    if (S < 1) S = 1;
+    return S;
+}
+
+// sweep_bf16.hip: the same products with X in bfloat16 (and the skinny
+// operand rounded to bfloat16), FP32 accumulation on the matrix cores.
+// pack: workspace of bf16_pack_elems(C) 16-bit words for the right sweep's
+// rounded panel.
+size_t bf16_pack_elems(int64_t C);
 size_t sweep_right_bf16_partial_floats(const Dev& d, int64_t R, int64_t C);
 hipError_t sweep_right_bf16(const Dev& d, int64_t R, int64_t C, const uint16_t* Xb,
-                            int64_t ldx, int k, const float* A, int64_t lda, float* Y,
-                            int64_t ldy, float* partial, uint16_t* abuf);
+                            int64_t ldx, int k, const float* A, int64_t lda, bool a_trans,
+                            float* Y, int64_t ldy, float* partial, uint16_t* pack);
 size_t sweep_left_bf16_partial_floats(const Dev& d, int64_t R, int64_t C);
 hipError_t sweep_left_bf16(const Dev& d, int64_t R, int64_t C, const uint16_t* Xb,
                            int64_t ldx, int k, const float* B, int64_t ldb, float* Z,
-                           int64_t ldz, bool z_trans, float* partial, uint16_t* bbuf);
+                           int64_t ldz, bool z_trans, float* partial);
 hipError_t to_bf16(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx,
                    uint16_t* Xb, int64_t ldxb);
 hipError_t transpose(const Dev& d, int64_t R, int64_t C, const float* A, int64_t lda,

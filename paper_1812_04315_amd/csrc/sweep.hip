@@ -398,17 +398,6 @@ __global__ __launch_bounds__(kThreads) void k_reduce_slices(
     else out[r * ldo + c] = s;
 }
 
-// Slices of the reduction dimension: the grid should fill every CU with as
-// many workgroups as fit at once (occupancy from the runtime) in one round,
-// since a second, partly filled round costs as much as a full one.
-int64_t pick_splits(int64_t tiles, int64_t kunits, int num_cus, int occ) {
-    const int64_t slots = (int64_t)num_cus * (occ > 0 ? occ : 1);
-    int64_t S = slots / tiles;
-    if (S > kunits) S = kunits;
-    if (S < 1) S = 1;
-    return S;
-}
-
 template <class K>
 int occupancy(K kernel) {
     int blocks = 0;
@@ -467,7 +456,9 @@ LeftPlan left_plan(const Dev& d, int64_t R, int64_t C, int k) {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-hipError_t reduce(const Dev& d, int64_t rows, int k, int64_t S, int nt, const float* partial,
+}  // namespace
+
+hipError_t reduce_slices(const Dev& d, int64_t rows, int k, int64_t S, int nt, const float* partial,
                   float* out, int64_t ldo, bool trans) {
     const int64_t tot = rows * nt;
     hipLaunchKernelGGL(k_reduce_slices, dim3((unsigned)((tot + kThreads - 1) / kThreads)),
@@ -475,8 +466,6 @@ hipError_t reduce(const Dev& d, int64_t rows, int k, int64_t S, int nt, const fl
                        trans ? 1 : 0);
     return hipGetLastError();
 }
-
-}  // namespace
 
 size_t sweep_right_partial_floats(const Dev& d, int64_t R, int64_t C) {
     const RightPlan p16 = right_plan(d, R, C, 16), p32 = right_plan(d, R, C, 32);
@@ -512,7 +501,7 @@ hipError_t sweep_right(const Dev& d, int64_t R, int64_t C, const float* X, int64
 #undef LAUNCH_R
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || direct) return e;
-    return reduce(d, R, k, p.S, p.nt, partial, Y, ldy, false);
+    return reduce_slices(d, R, k, p.S, p.nt, partial, Y, ldy, false);
 }
 
 size_t sweep_left_partial_floats(const Dev& d, int64_t R, int64_t C) {
@@ -535,7 +524,7 @@ hipError_t sweep_left(const Dev& d, int64_t R, int64_t C, const float* X, int64_
 #undef LAUNCH_L
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return reduce(d, C, k, p.S, p.nt, partial, Z, ldz, z_trans);
+    return reduce_slices(d, C, k, p.S, p.nt, partial, Z, ldz, z_trans);
 }
 
 // ---------------------------------------------------------------------------
@@ -577,14 +566,6 @@ __global__ __launch_bounds__(kThreads) void k_check_input(int64_t R, int64_t C,
         for (int off = 32; off >= 1; off >>= 1) w |= __shfl_xor(w, off, kWave);
         if ((threadIdx.x & 63) == 0) raise_status(ctl, w);
     }
-}
-
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
-    const uint32_t lsb = (u >> 16) & 1u;
-    u += 0x7fffu + lsb;
-    return (uint16_t)(u >> 16);
 }
 
 __global__ __launch_bounds__(kThreads) void k_to_bf16(int64_t R, int64_t C,
