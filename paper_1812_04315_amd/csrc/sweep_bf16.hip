@@ -184,20 +184,32 @@ __global__ __launch_bounds__(kThreads) void k_sweep_right_bf16(
 }
 
 // ---------------------------------------------------------------------------
-// Left sweep, Z = X^T B, without LDS staging.  A wave owns 256 columns of X.
-// Load instruction i covers two rows (lanes 0-31 the first, lanes 32-63 the
+// Left sweep, Z = X^T B, without LDS staging, on v_mfma_f32_32x32x16_bf16
+// (lane l holds eight bf16 values: A[m = l % 32][k = 8 (l / 32) + i],
+// B[k = 8 (l / 32) + i][n = l % 32]).  A wave owns 256 columns of X.  Load
+// instruction i covers two rows (lanes 0-31 the first, lanes 32-63 the
 // second) x 256 columns, 16 bytes per lane, so lanes l and l + 32 hold the
-// same 8 columns of different rows.  After four instructions (rows
-// r0 + g + 2 i, g = l / 32) lane l has, for each of its columns, the four
-// values that MFMA reduction slots (g, i) need: MFMA j (j = 0..7) treats
-// column 8 (l % 32) + j as its M index l % 32, so one group of eight rows
+// same 8 columns of different rows.  After eight instructions (rows
+// r0 + g + 2 i, g = l / 32, i = 0..7) lane l has, for each of its columns,
+// the eight values that reduction slots (g, i) need: MFMA j (j = 0..7) takes
+// column 8 (l % 32) + j as its M index l % 32, so one group of sixteen rows
 // feeds eight MFMAs with no data exchange.  The B operand is
 // bf16(B[r0 + g + 2 i][n = l % 32]).  The four waves of a workgroup take
 // interleaved row groups of the slice and are summed through LDS in wave
 // order.
 // ---------------------------------------------------------------------------
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v16f mfma_bf16_x16(v4u_t a, v4u_t b, v16f c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a),
+                                                   __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+
+constexpr int kLG = 16;     // rows per group (two per load instruction)
+
 template <bool VEC>
-__global__ __launch_bounds__(kThreads) void k_sweep_left_bf16(
+__global__ __launch_bounds__(kThreads, 2) void k_sweep_left_bf16(
     int64_t R, int64_t C, const uint16_t* __restrict__ X, int64_t ldx, int k,
     const float* __restrict__ B, int64_t ldb, float* __restrict__ partial, int64_t rspan) {
     __shared__ float red[8 * 16 * 64];        // 32 KB: one wave's accumulators
@@ -209,9 +221,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep_left_bf16(
     const int64_t col0 = (int64_t)blockIdx.x * 256;
     const int64_t r_lo = (int64_t)blockIdx.y * rspan;
     const int64_t r_hi = min(R, r_lo + rspan);
-    const int64_t ngr = (r_hi - r_lo + 7) / 8;       // groups of 8 rows in the slice
+    const int64_t ngr = (r_hi - r_lo + kLG - 1) / kLG;   // row groups in the slice
     const int64_t col = col0 + 8 * n;
-    const bool full = VEC && col0 + 256 <= C;       // uniform across the workgroup
+    const bool full = VEC && col0 + 256 <= C;            // uniform across the workgroup
 
     v16f acc[8];
 #pragma unroll
@@ -219,24 +231,22 @@ __global__ __launch_bounds__(kThreads) void k_sweep_left_bf16(
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
 
-    v4u xn[4], xc[4];
-    unsigned bn[2], bcur[2];
+    v4u xn[8], xc[8];
+    float bn[8], bc[8];          // raw B values; rounded and masked at use
+    int64_t bn_row0 = 0, bc_row0 = 0;
     auto load_b = [&](int64_t rb) {
-        unsigned h[4];
+        bn_row0 = rb;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 8; ++i) {
             const int64_t row = rb + g + 2 * i;
-            const float v = B[(row < R ? row : R - 1) * ldb + nc];
-            h[i] = (row < r_hi && n < k) ? f32_to_bf16_rne(v) : 0u;
+            bn[i] = B[(row < R ? row : R - 1) * ldb + nc];
         }
-        bn[0] = h[0] | (h[1] << 16);
-        bn[1] = h[2] | (h[3] << 16);
     };
     auto load_fast = [&](int64_t gi) {
         gi = gi < ngr ? gi : ngr - 1;
-        const int64_t rb = r_lo + 8 * gi;
+        const int64_t rb = r_lo + kLG * gi;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 8; ++i) {
             const int64_t row = rb + g + 2 * i;
             const uint16_t* xr = X + (row < R ? row : R - 1) * ldx;
             xn[i] = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(xr + col));
@@ -244,9 +254,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep_left_bf16(
         load_b(rb);
     };
     auto load_slow = [&](int64_t gi) {
-        const int64_t rb = r_lo + 8 * gi;
+        const int64_t rb = r_lo + kLG * gi;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 8; ++i) {
             const int64_t row = rb + g + 2 * i;
             const uint16_t* xr = X + (row < R ? row : R - 1) * ldx;
             unsigned w[4];
@@ -263,24 +273,31 @@ __global__ __launch_bounds__(kThreads) void k_sweep_left_bf16(
     };
     auto take = [&]() {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) xc[i] = xn[i];
-        bcur[0] = bn[0];
-        bcur[1] = bn[1];
+        for (int i = 0; i < 8; ++i) {
+            xc[i] = xn[i];
+            bc[i] = bn[i];
+        }
+        bc_row0 = bn_row0;
     };
     auto compute = [&]() {
-        const v4s b = as_v4s(bcur[0], bcur[1]);
+        unsigned h[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const bool live = bc_row0 + g + 2 * i < r_hi && n < k;
+            h[i] = live ? f32_to_bf16_rne(bc[i]) : 0u;
+        }
+        const v4u_t b = v4u_t{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                              h[6] | (h[7] << 16)};
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int d = j >> 1;
-            unsigned lo, hi;
-            if (j & 1) {
-                lo = (xc[0][d] >> 16) | (xc[1][d] & 0xffff0000u);
-                hi = (xc[2][d] >> 16) | (xc[3][d] & 0xffff0000u);
-            } else {
-                lo = (xc[0][d] & 0xffffu) | (xc[1][d] << 16);
-                hi = (xc[2][d] & 0xffffu) | (xc[3][d] << 16);
+            v4u_t a;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const unsigned x0 = xc[2 * p][d], x1 = xc[2 * p + 1][d];
+                a[p] = (j & 1) ? ((x0 >> 16) | (x1 & 0xffff0000u)) : ((x0 & 0xffffu) | (x1 << 16));
             }
-            acc[j] = mfma_bf16(as_v4s(lo, hi), b, acc[j]);
+            acc[j] = mfma_bf16_x16(a, b, acc[j]);
         }
     };
 
@@ -353,9 +370,9 @@ Plan left_plan(const Dev& d, int64_t R, int64_t C) {
     static const int occ = occupancy(k_sweep_left_bf16<true>);
     Plan p;
     p.tiles = (C + 255) / 256;
-    const int64_t groups = (R + 31) / 32;          // 4 waves x 8 rows per round
+    const int64_t groups = (R + 4 * kLG - 1) / (4 * kLG);   // 4 waves x 16 rows per round
     p.S = pick_splits(p.tiles, groups, d.num_cus, occ);
-    p.span = 32 * ((groups + p.S - 1) / p.S);
+    p.span = 4 * kLG * ((groups + p.S - 1) / p.S);
     p.S = (R + p.span - 1) / p.span;
     return p;
 }
