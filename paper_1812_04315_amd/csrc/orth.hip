@@ -2,9 +2,11 @@
 // "QR decomposition", "orthonormal bases" of each sketch and half-step).
 //
 // CholeskyQR2 on an N x l FP32 panel (l <= 32), one persistent launch:
-//   pass 1: W = [Y P]^T [Y P] in FP64 (P = replacement pool), right-looking
-//           Cholesky of W with the numerical-rank rule, Q1 = Y^ R^-1 where Y^
-//           is Y with deficient columns swapped for pool columns;
+//   pass 1: W = Y^T Y in FP64, right-looking Cholesky with the numerical-
+//           rank rule; if a column is deficient, the same on the augmented
+//           W = [Y P]^T [Y P] (P = replacement pool) with the swaps;
+//           Q1 = Y^ R^-1 where Y^ is Y with deficient columns swapped for
+//           pool columns;
 //   pass 2: W = Q1^T Q1, Cholesky, Q = Q1 R2^-1.
 // The FP64 Gram of FP32 data has exact products, so pass 1 already gives
 // orthogonality near FP32 rounding for condition numbers far beyond what the
@@ -66,6 +68,7 @@ struct Shared {
     double tile[kTile][kMaxW + 1];
     double Ri[32][33];
     double rvec[kMaxW];
+    double dinv[32];
     double ref[kMaxW];
     int sel[32];
     int flag;
@@ -123,6 +126,7 @@ __device__ void gram_partial(const OrthArgs& g, Shared& sh, const float* A, int 
         for (int s = 0; s < kPairsPerThread; ++s) {
             if (pb[s] >= 0) {
                 double t = acc[s];
+#pragma unroll 2
                 for (int rr = 0; rr < kTile; ++rr) t = fma(sh.tile[rr][pa[s]], sh.tile[rr][pb[s]], t);
                 acc[s] = t;
             }
@@ -202,6 +206,91 @@ __device__ bool gram_exchange(const OrthArgs& g, Shared& sh, int w, unsigned tag
     return true;
 }
 
+// R^-1 of the upper-triangular R held in sh.M[0..l-1][0..l-1] into sh.Ri, by
+// one wavefront: lane c owns column c in registers and back-substitutes
+// x_i = -(sum_{t > i} R[i][t] x_t) / R[i][i], x_c = 1 / R[c][c]; rows of R
+// are broadcast reads from LDS.  Fully unrolled (register indices are
+// compile-time constants).
+__device__ void inverse_upper(Shared& sh, int l) {
+    const int c = threadIdx.x;
+    if (c < l) sh.dinv[c] = 1.0 / sh.M[c][c];
+    __builtin_amdgcn_wave_barrier();
+    double x[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) x[i] = 0.0;
+#pragma unroll
+    for (int i = 31; i >= 0; --i) {
+        if (i < l) {
+            double s = 0.0;
+#pragma unroll
+            for (int t = i + 1; t < 32; ++t) {
+                const double r = sh.M[i][t];
+                s = fma(t < l ? r : 0.0, x[t], s);
+            }
+            const double di = sh.dinv[i];
+            x[i] = (i == c) ? di : (i < c ? -s * di : 0.0);
+        }
+    }
+    if (c < l) {
+#pragma unroll
+        for (int t = 0; t < 32; ++t)
+            if (t < l) sh.Ri[t][c] = x[t];
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Right-looking Cholesky of the l x l Gram in sh.M by one wavefront with the
+// matrix in registers (lane i holds row i, which is also column i of the
+// symmetric trailing part); fully unrolled.  detect: a pivot failing the
+// rank rule sets sh.flag and returns (the caller switches to the augmented
+// Gram); otherwise a pivot <= tau2 * W_jj is a breakdown (pivot set to 1 and
+// the column zeroed).  R is left in sh.M (row j = R[j][.]), R^-1 in sh.Ri.
+__device__ void cholesky_regs(const OrthArgs& g, Shared& sh, bool detect) {
+    const int lane = threadIdx.x;   // wave 0 only
+    const int l = g.l;
+    if (lane < 32) sh.sel[lane] = 0;
+    double Mr[32];
+#pragma unroll
+    for (int b = 0; b < 32; ++b) Mr[b] = (lane < l && b < l) ? sh.M[lane][b] : 0.0;
+    const double myref = lane < l ? sh.M[lane][lane] : 0.0;
+    if (lane < l) sh.ref[lane] = myref;
+    if (__any(lane < l && !isfinite(myref)) && lane == 0) raise_status(g.ctl, CNMF_ST_NONFINITE);
+    const double thr = g.tau2 * wave_max(myref);
+    __builtin_amdgcn_wave_barrier();
+    bool stop = false;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        if (j < l && !stop) {
+            double d = lane_d(Mr[j], j);                     // M[j][j]
+            if (detect) {
+                if (!(d > thr)) stop = true;                 // uniform
+            } else if (!(d > g.tau2 * sh.ref[j])) {
+                if (lane == 0) raise_status(g.ctl, CNMF_ST_BREAKDOWN);
+                d = 1.0;
+                if (lane > j) Mr[j] = 0.0;
+            }
+            if (!stop) {
+                const double rjj = sqrt(d);
+                const double ri = (lane > j && lane < l) ? Mr[j] / rjj : (lane == j ? rjj : 0.0);
+                if (lane < 32) {
+                    sh.rvec[lane] = ri;
+                    sh.M[j][lane] = ri;                      // row j of R
+                }
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int b = j + 1; b < 32; ++b) Mr[b] = fma(-ri, sh.rvec[b], Mr[b]);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    if (stop) {
+        if (lane == 0) sh.flag = 1;
+        __builtin_amdgcn_wave_barrier();
+        return;
+    }
+    inverse_upper(sh, l);
+}
+
 // Right-looking Cholesky of sh.M (w x w) over the first l pivots by one
 // wavefront (lane i owns row i), with the rank rule when allow_swap; R^-1 of
 // the leading l x l factor into sh.Ri, swap flags into sh.sel.
@@ -230,6 +319,13 @@ __device__ void cholesky_wave(const OrthArgs& g, Shared& sh, int w, bool allow_s
             if (!(d > thr)) flag = 1;
         } else if (!(d > g.tau2 * sh.ref[j])) {
             flag = 2;
+        }
+        if (flag == 1 && w == l) {
+            // no pool columns in this Gram: report, the caller redoes the
+            // factorisation on the augmented Gram
+            if (lane == 0) sh.flag = 1;
+            __builtin_amdgcn_wave_barrier();
+            return;
         }
         if (flag == 1) {
             // swap rows / columns j and l + j of the augmented matrix
@@ -277,39 +373,35 @@ __device__ void cholesky_wave(const OrthArgs& g, Shared& sh, int w, bool allow_s
             if (j < l) sh.M[j][lane] = rrow[j];
     }
     __builtin_amdgcn_wave_barrier();
-    // R^-1 by back substitution, lane c owns column c
-    if (lane < l) {
-        const int c = lane;
-        for (int i = 0; i < l; ++i) sh.Ri[i][c] = 0.0;
-        sh.Ri[c][c] = 1.0 / sh.M[c][c];
-        for (int i = c - 1; i >= 0; --i) {
-            double s = 0.0;
-            for (int t = i + 1; t <= c; ++t) s = fma(sh.M[i][t], sh.Ri[t][c], s);
-            sh.Ri[i][c] = -s / sh.M[i][i];
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
+    inverse_upper(sh, l);
 }
 
-// Q[r][:] = Ysrc^[r][:] * Ri over this workgroup's rows (FP64 arithmetic).
+// Q[r][:] = Ysrc^[r][:] * Ri over this workgroup's rows (FP64 arithmetic):
+// tiles of 32 rows staged in LDS, one output element per thread and step.
 __device__ void apply_rows(const OrthArgs& g, Shared& sh, const float* Ysrc, bool use_pool,
                            int64_t r0, int64_t r1, float* Qdst, float* QT) {
     const int l = g.l;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += kThreads) {
-        double y[32];
-#pragma unroll
-        for (int i = 0; i < 32; ++i) {
-            if (i < l) y[i] = (use_pool && sh.sel[i]) ? (double)g.P[r * g.p_rs + i * g.p_cs]
-                                                      : (double)Ysrc[r * l + i];
-            else y[i] = 0.0;
+    for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kTile * l; e += kThreads) {
+            const int rr = e / l, i = e - rr * l;
+            const int64_t r = t0 + rr;
+            double v = 0.0;
+            if (r < r1)
+                v = (use_pool && sh.sel[i]) ? (double)g.P[r * g.p_rs + i * g.p_cs]
+                                            : (double)Ysrc[r * l + i];
+            sh.tile[rr][i] = v;
         }
-        for (int c = 0; c < l; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int i = 0; i < 32; ++i)
-                if (i <= c) s = fma(y[i], sh.Ri[i][c], s);
-            Qdst[r * l + c] = (float)s;
-            if (QT) QT[(int64_t)c * g.ldqt + r] = (float)s;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kTile * l; e += kThreads) {
+            const int rr = e / l, c = e - rr * l;
+            const int64_t r = t0 + rr;
+            if (r < r1) {
+                double s = 0.0;
+                for (int i = 0; i <= c; ++i) s = fma(sh.tile[rr][i], sh.Ri[i][c], s);
+                Qdst[r * l + c] = (float)s;
+                if (QT) QT[(int64_t)c * g.ldqt + r] = (float)s;
+            }
         }
     }
 }
@@ -324,26 +416,40 @@ __global__ __launch_bounds__(kThreads) void k_orth(OrthArgs g) {
     double acc[kPairsPerThread];
     int pa[kPairsPerThread], pb[kPairsPerThread];
 
-    // pass 1: augmented Gram, Cholesky with swaps, Q1 = Y^ R^-1 (into Q)
-    gram_partial(g, sh, g.Y, 2 * l, r0, r1, acc, pa, pb);
-    if (!gram_exchange(g, sh, 2 * l, (g.seq << 10) | 1u, (g.seq << 10) | 2u, acc, pa, pb)) return;
-    if (threadIdx.x < 64) cholesky_wave(g, sh, 2 * l, true);
-    __syncthreads();
-    if (blockIdx.x == 0 && g.replaced && threadIdx.x < l) g.replaced[threadIdx.x] = sh.sel[threadIdx.x];
-    apply_rows(g, sh, g.Y, true, r0, r1, g.Q, nullptr);
-    __threadfence_block();
-    __syncthreads();
-
-    // pass 2 on Q1 (no swaps), in place
-    gram_partial(g, sh, g.Q, l, r0, r1, acc, pa, pb);
-    if (!gram_exchange(g, sh, l, (g.seq << 10) | 3u, (g.seq << 10) | 4u, acc, pa, pb)) return;
-    if (threadIdx.x < 64) cholesky_wave(g, sh, l, false);
-    __syncthreads();
-    apply_rows(g, sh, g.Q, false, r0, r1, g.Q, g.QT);
+    // Stage 0: Gram of Y, Cholesky with the rank test (pass 1).
+    // Stage 1 (only if a column of Y is deficient; every workgroup factors
+    //   the same sums, so the decision is uniform): the same on the Gram of
+    //   [Y P], with the swaps.  Stage 0 or 1 ends with Q1 = Y^ R^-1 in Q.
+    // Stage 2: Gram of Q1, Cholesky, Q = Q1 R2^-1 in place (pass 2).
+    // One loop body keeps a single copy of each step's code.
+    if (threadIdx.x == 0) sh.flag = 0;
+    int stage = 0;
+    while (stage < 3) {
+        const bool aug = stage == 1;
+        const int w = aug ? 2 * l : l;
+        const float* A = stage == 2 ? g.Q : g.Y;
+        const unsigned tag = (g.seq << 10) | (unsigned)(2 * stage + 1);
+        gram_partial(g, sh, A, w, r0, r1, acc, pa, pb);
+        if (!gram_exchange(g, sh, w, tag, tag + 1, acc, pa, pb)) return;
+        if (threadIdx.x < 64) {
+            if (aug) cholesky_wave(g, sh, w, true);
+            else cholesky_regs(g, sh, stage == 0);
+        }
+        __syncthreads();
+        if (stage == 0 && sh.flag) {
+            stage = 1;
+            continue;
+        }
+        if (stage < 2 && blockIdx.x == 0 && g.replaced && threadIdx.x < l)
+            g.replaced[threadIdx.x] = sh.sel[threadIdx.x];
+        apply_rows(g, sh, A, stage < 2, r0, r1, g.Q, stage == 2 ? g.QT : nullptr);
+        __syncthreads();
+        stage = stage < 2 ? 2 : 3;
+    }
 }
 
 unsigned orth_blocks(const Dev& d, int64_t N) {
-    int64_t b = (N + 255) / 256;
+    int64_t b = (N + 31) / 32;     // at least 32 rows per workgroup
     if (b > d.num_cus) b = d.num_cus;
     if (b > 256) b = 256;
     return (unsigned)(b < 1 ? 1 : b);
