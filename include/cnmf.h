@@ -223,6 +223,53 @@ int cnmf_nnls(cnmf_ctx* ctx, int64_t rows, int32_t p, float* Z, int64_t z_rs,
               int32_t inner_max, int32_t inner_min, int32_t forced,
               int32_t* steps_out, double* L_out, double* pg2_out);
 
+/* ---- batched form: many independent instances ------------------------
+ * Randomized subspace iteration (Algorithm 2) and compressed NeNMF
+ * (Algorithm 1) for `count` independent instances of uneven n, m, p.  Each
+ * subproblem phase of all instances runs in one persistent launch: a
+ * schedule packs every instance's workgroups into rounds of resident
+ * workgroups (row tiles of 64 x tiles rows, tiles in {1, 2, 4} per side,
+ * chosen by cnmf_batch_tune), and the outer loop of cnmf_batch_solve is
+ * captured once in a HIP graph and replayed.  Per-instance arguments as in
+ * cnmf_rsi and cnmf_solve; all pointers are caller-owned device memory that
+ * must stay valid for the life of the batch. */
+typedef struct cnmf_instance {
+    int64_t n, m;
+    int32_t p, nu;            /* 1 <= p, p + nu <= min(n, m), p + nu <= 32     */
+    const float* X;           /* n x m, row pitch ldx (multiple of 4, 16-byte  */
+    int64_t ldx;              /* aligned rows)                                */
+    const float* omega_L;     /* m x l                                        */
+    const float* omega_R;     /* l x n                                        */
+    float* Q_L;               /* n x l   (written by cnmf_batch_rsi)          */
+    float* Q_R;               /* m x l                                        */
+    float* X_L;               /* l x m                                        */
+    float* X_R;               /* n x l                                        */
+    float* G;                 /* n x p, in/out                                */
+    float* F;                 /* p x m, in/out                                */
+    int32_t* steps;           /* optional T x 2 inner step counts (out)       */
+    const int32_t* replay;    /* optional T x 2 forced inner step counts      */
+} cnmf_instance;
+
+typedef struct cnmf_batch cnmf_batch;
+
+/* Plan a batch: copies the descriptors (host array), allocates the batch's
+ * device state, builds the schedules with tiles_g / tiles_f (1, 2 or 4; 0
+ * picks the smallest that fits).  prm: q, outer_iters, inner_*, stop_rule,
+ * tau2 apply to every instance (its p and nu come from the descriptor). */
+int cnmf_batch_create(cnmf_ctx* ctx, const cnmf_instance* inst, int32_t count,
+                      const cnmf_params* prm, int32_t tiles_g, int32_t tiles_f,
+                      cnmf_batch** out);
+int cnmf_batch_destroy(cnmf_batch* b);
+/* Algorithm 2 for every instance (Q_L, Q_R, X_L, X_R). */
+int cnmf_batch_rsi(cnmf_batch* b);
+/* Autotune: times a few outer iterations of the batched solve for every
+ * (tiles_g, tiles_f) that fits, on scratch copies of G and F, keeps the
+ * fastest schedule and writes it to tiles_out[2] (host). */
+int cnmf_batch_tune(cnmf_batch* b, int32_t tune_iters, int32_t* tiles_out);
+/* Compressed NeNMF outer loop for every instance; use_graph != 0 captures
+ * the whole loop in a HIP graph on first use and replays it afterwards. */
+int cnmf_batch_solve(cnmf_batch* b, int32_t use_graph);
+
 #ifdef __cplusplus
 }
 #endif

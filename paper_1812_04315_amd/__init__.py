@@ -32,6 +32,8 @@ EXPORTED = [
     "cnmf_to_bf16", "cnmf_solve", "cnmf_rre", "cnmf_sweep_right", "cnmf_sweep_left",
     "cnmf_sweep_right_bf16", "cnmf_sweep_left_bf16",
     "cnmf_orth", "cnmf_lipschitz", "cnmf_nnls",
+    "cnmf_batch_create", "cnmf_batch_destroy", "cnmf_batch_rsi", "cnmf_batch_tune",
+    "cnmf_batch_solve",
 ]
 
 
@@ -50,6 +52,17 @@ class Params(ctypes.Structure):
         ("tau2", ctypes.c_double), ("stop_rule", ctypes.c_int32),
         ("sweep_prec", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+    ]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("m", ctypes.c_int64), ("p", ctypes.c_int32),
+        ("nu", ctypes.c_int32), ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64),
+        ("omega_L", ctypes.c_void_p), ("omega_R", ctypes.c_void_p),
+        ("Q_L", ctypes.c_void_p), ("Q_R", ctypes.c_void_p), ("X_L", ctypes.c_void_p),
+        ("X_R", ctypes.c_void_p), ("G", ctypes.c_void_p), ("F", ctypes.c_void_p),
+        ("steps", ctypes.c_void_p), ("replay", ctypes.c_void_p),
     ]
 
 
@@ -92,6 +105,12 @@ def lib() -> ctypes.CDLL:
             "cnmf_orth": (ctypes.c_int, [P, I64, I32, P, P, I32, D, P, P]),
             "cnmf_lipschitz": (ctypes.c_int, [P, I32, P, P]),
             "cnmf_nnls": (ctypes.c_int, [P, I64, I32, P, I64, I64, P, P, D, I32, I32, I32, P, P, P]),
+            "cnmf_batch_create": (ctypes.c_int, [P, ctypes.POINTER(Instance), I32,
+                                                 ctypes.POINTER(Params), I32, I32, ctypes.POINTER(P)]),
+            "cnmf_batch_destroy": (ctypes.c_int, [P]),
+            "cnmf_batch_rsi": (ctypes.c_int, [P]),
+            "cnmf_batch_tune": (ctypes.c_int, [P, I32, ctypes.POINTER(I32)]),
+            "cnmf_batch_solve": (ctypes.c_int, [P, I32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -448,3 +467,62 @@ def nnls(Z, W, B, tol: float, inner_max: int, inner_min: int = 1, forced: int = 
     _call("cnmf_nnls", context().h, rows, p, _ptr(Z), rs, cs, _ptr(W), _ptr(B), tol,
           inner_max, inner_min, forced, _ptr(steps), _ptr(L), _ptr(pg2))
     return steps, L, pg2
+
+
+# ---------------------------------------------------------------------------
+# Batched form
+# ---------------------------------------------------------------------------
+class Batch:
+    """Many independent compressed-NeNMF instances planned together.
+
+    ``instances``: list of dicts with device tensors X (n x m, may be None if
+    the compressed data is supplied), omega_L, omega_R, Q_L, Q_R, X_L, X_R,
+    G, F and optional int32 ``steps`` / ``replay`` (T x 2), plus ``p`` and
+    ``nu``.  The tensors must stay alive while the batch is used."""
+
+    def __init__(self, instances, *, q: int = 2, outer_iters: int = 100, inner_max: int = 500,
+                 inner_min: int = 1, inner_ratio: float = 1e-3, stop_rule: int = STOP_GLOBAL,
+                 tau2: float = 1e-9, tiles_g: int = 0, tiles_f: int = 0):
+        self._keep = list(instances)
+        arr = (Instance * len(instances))()
+        for k, d in enumerate(instances):
+            G, F = d["G"], d["F"]
+            n, p = G.shape
+            m = F.shape[1]
+            X = d.get("X")
+            arr[k] = Instance(n, m, d["p"], d["nu"], _ptr(X) if X is not None else None,
+                              _ld(X) if X is not None else m,
+                              _ptr(d["omega_L"]) if d.get("omega_L") is not None else None,
+                              _ptr(d["omega_R"]) if d.get("omega_R") is not None else None,
+                              _ptr(d["Q_L"]), _ptr(d["Q_R"]), _ptr(d["X_L"]), _ptr(d["X_R"]),
+                              _ptr(G), _ptr(F),
+                              _ptr(d["steps"]) if d.get("steps") is not None else None,
+                              _ptr(d["replay"]) if d.get("replay") is not None else None)
+        prm = params(1, 0, q, outer_iters, inner_max, inner_min, inner_ratio, tau2, stop_rule)
+        self._ctx = context()
+        h = ctypes.c_void_p()
+        _call("cnmf_batch_create", self._ctx.h, arr, len(instances), ctypes.byref(prm),
+              tiles_g, tiles_f, ctypes.byref(h))
+        self.h = h
+
+    def rsi(self):
+        _call("cnmf_batch_rsi", self.h)
+
+    def tune(self, iters: int = 3):
+        out = (ctypes.c_int32 * 2)()
+        _call("cnmf_batch_tune", self.h, iters, out)
+        return int(out[0]), int(out[1])
+
+    def solve(self, use_graph: bool = True):
+        _call("cnmf_batch_solve", self.h, 1 if use_graph else 0)
+
+    def close(self):
+        if self.h:
+            lib().cnmf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass

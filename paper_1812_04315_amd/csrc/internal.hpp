@@ -235,10 +235,26 @@ struct PhaseArgs {
     double* tol_out;
     double* pg2_out;         // ||P grad(Z_0)||^2
     int kind;                // 0 solve, 1 projected-gradient norm only, 2 partial product only
-    double* tol_init_from;   // with kind 1: tol = ratio*sqrt(pg2 + *tol_init_from) -> ctl->tol
+    double* tol_init_from;   // with kind 1: tol = ratio*sqrt(pg2 + *tol_init_from) -> tol_init_out[0..1]
+    double* tol_init_out;
+    unsigned nblk;           // workgroups of this subproblem (batched launches)
     float* hist;
     unsigned long long* tick_out;
 };
+
+// Batched launch of many subproblems (see k_phase_batched): args[count] on
+// the device, sched[rounds][slots] entries (instance << 12 | block) or
+// 0xffffffff; epoch / done: device words owned by the batch.
+struct BatchLaunch {
+    const PhaseArgs* args;
+    const uint32_t* sched;
+    int count;
+    int rounds;
+    int slots;
+    unsigned* epoch;
+    unsigned* done;
+};
+hipError_t phase_batched(const Dev& d, const BatchLaunch& b, int tiles, int dlag);
 
 bool phase_grid(const Dev& d, int64_t rows, int* tiles, unsigned* nblk);
 hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles);

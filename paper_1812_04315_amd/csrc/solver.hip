@@ -159,8 +159,11 @@ __device__ double lambda_max_wave(double (*A)[33], int p, double* v, double* wv,
 
 namespace {
 
+// One subproblem (G rows or F columns) on workgroup blk of nblk; seq tags
+// the exchange words of this launch.
 template <int PT, int TILES, int DLAG>
-__global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
+__device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned blk,
+                                           const unsigned nblk, const unsigned seq) {
     constexpr int NH = (DLAG + 1) > 2 ? (DLAG + 1) : 2;     // iterates kept
     constexpr int NR = PT * 4;                              // registers per row tile
     constexpr int NSLOT = 2 * DLAG + 2;
@@ -179,8 +182,8 @@ __global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
     const int wave = threadIdx.x >> 6;
     const int q16 = lane & 15;
     const int g4 = lane >> 4;
-    const unsigned nblk = gridDim.x;
     const int p = a.p;
+    __syncthreads();   // LDS of a previous subproblem on this workgroup
     Control* ctl = a.ctl;
     bool ok = true;
 
@@ -195,13 +198,13 @@ __global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
     if (a.mode == 0) {
         for (int e = threadIdx.x; e < p * p; e += kThreads) sW[e / p][e % p] = a.Wgiven[e];
     } else if (a.kind != 2) {
-        // this workgroup's share: entries e = blockIdx.x + nblk * j, one wave each
-        for (int e = blockIdx.x + nblk * wave; e < nS; e += nblk * 4) {
+        // this workgroup's share: entries e = blk + nblk * j, one wave each
+        for (int e = (int)blk + (int)nblk * wave; e < nS; e += (int)nblk * 4) {
             const int mr = e / p, nc = e % p;
             double t = 0.0;
             for (int j = lane; j < a.nin; j += 64) t += (double)a.part_in[(size_t)j * 1024 + mr * 32 + nc];
             t = wave_sum(t);
-            if (lane == 0) slot_store(&a.slot_s[e], a.seq, __float_as_uint((float)t));
+            if (lane == 0) slot_store(&a.slot_s[e], seq, __float_as_uint((float)t));
         }
         // read all shares back
         unsigned spins = 0;
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
             int mine_ok = 1;
             for (int e = threadIdx.x; e < nS; e += kThreads) {
                 const uint64_t w = slot_load(&a.slot_s[e]);
-                if ((unsigned)(w >> 32) == a.seq) sS[e / p][e % p] = __uint_as_float((uint32_t)w);
+                if ((unsigned)(w >> 32) == seq) sS[e / p][e % p] = __uint_as_float((uint32_t)w);
                 else mine_ok = 0;
             }
             if (__syncthreads_and(mine_ok)) break;
@@ -266,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
                 wA[hp][h][s] = a.wt ? sW[c][k] : sW[k][c];
             }
 
-    const int64_t row_base = (int64_t)blockIdx.x * (64 * TILES) + (int64_t)wave * (16 * TILES);
+    const int64_t row_base = (int64_t)blk * (64 * TILES) + (int64_t)wave * (16 * TILES);
     float z[TILES][NR], bb[TILES][NR];
 #pragma unroll
     for (int t = 0; t < TILES; ++t) {
@@ -332,8 +335,8 @@ __global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
         if (threadIdx.x == 0) {
             const double tot = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
             const uint64_t bits = (uint64_t)__double_as_longlong(tot);
-            const unsigned tag = (a.seq << 10) | ((unsigned)step & 1023u);
-            uint64_t* sl = a.slot_pg + ((size_t)(step % NSLOT) * 256 + blockIdx.x) * 2;
+            const unsigned tag = (seq << 10) | ((unsigned)step & 1023u);
+            uint64_t* sl = a.slot_pg + ((size_t)(step % NSLOT) * 256 + blk) * 2;
             slot_store(sl + 0, tag, (uint32_t)(bits >> 32));
             slot_store(sl + 1, tag, (uint32_t)(bits & 0xffffffffu));
         }
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
     // grid total of step `step` (wave 0 polls; result broadcast through LDS)
     auto collect = [&](int step) -> double {
         if (wave == 0) {
-            const unsigned tag = (a.seq << 10) | ((unsigned)step & 1023u);
+            const unsigned tag = (seq << 10) | ((unsigned)step & 1023u);
             const uint64_t* base = a.slot_pg + (size_t)(step % NSLOT) * 256 * 2;
             unsigned spins = 0;
             int to = 0;
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
     int out_idx = 0;
 
     if (!(L > 0.0)) {
-        if (a.kind == 0 && blockIdx.x == 0 && threadIdx.x == 0)
+        if (a.kind == 0 && blk == 0 && threadIdx.x == 0)
             raise_status(ctl, (L != L) ? CNMF_ST_NONFINITE : CNMF_ST_ZERO_LIPS);
     } else if (ok && kmax > 0) {
         const float invL = (float)(1.0 / L);
@@ -479,7 +482,7 @@ __global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
                     const double tot = collect(jst);
                     if (s_flag) { ok = false; break; }
                     if (!(tot == tot)) {
-                        if (blockIdx.x == 0 && threadIdx.x == 0) raise_status(ctl, CNMF_ST_NONFINITE);
+                        if (blk == 0 && threadIdx.x == 0) raise_status(ctl, CNMF_ST_NONFINITE);
                     } else if (sqrt(tot) <= tol) {
                         stop_at = jst;
                         break;
@@ -574,21 +577,21 @@ __global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
             const int M = 16 * hm + 4 * (l >> 4) + i;
             const int N = 16 * hn + (l & 15);
             const float s = (sred[0][ri][l] + sred[1][ri][l]) + (sred[2][ri][l] + sred[3][ri][l]);
-            if (hn < PT) a.part_out[(size_t)blockIdx.x * 1024 + M * 32 + N] = s;
-            else a.part_out[(size_t)blockIdx.x * 1024 + M * 32 + N] = 0.f;
+            if (hn < PT) a.part_out[(size_t)blk * 1024 + M * 32 + N] = s;
+            else a.part_out[(size_t)blk * 1024 + M * 32 + N] = 0.f;
         }
     }
 
     if (threadIdx.x == 0) {
-        if (blockIdx.x == 0) {
+        if (blk == 0) {
             if (a.steps_out && a.kind == 0) a.steps_out[0] = steps;
             if (a.L_out) a.L_out[0] = L;
             if (a.tol_out) a.tol_out[0] = tol;
             if (a.pg2_out) a.pg2_out[0] = pg0;
             if (a.kind == 1 && a.tol_init_from) {
                 const double tt = a.ratio * sqrt(pg0 + *a.tol_init_from);
-                ctl->tol[0] = tt;
-                ctl->tol[1] = tt;
+                a.tol_init_out[0] = tt;
+                a.tol_init_out[1] = tt;
                 if (!isfinite(tt)) raise_status(ctl, CNMF_ST_NONFINITE);
             }
             if (a.kind == 0 && a.tol_state && steps >= 1 && steps <= a.inner_min)
@@ -596,6 +599,11 @@ __global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
         }
         if (a.tick_out) atomicMax(a.tick_out, (unsigned long long)wall_clock64());
     }
+}
+
+template <int PT, int TILES, int DLAG>
+__global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
+    phase_body<PT, TILES, DLAG>(a, blockIdx.x, gridDim.x, a.seq);
 }
 
 template <int PT, int TILES, int DLAG>
@@ -624,6 +632,61 @@ hipError_t launch1(const Dev& d, const PhaseArgs& a, int tiles, unsigned nblk) {
     }
 }
 
+// Batched form: many subproblems in one persistent launch.  Workgroup s
+// walks the rounds of a schedule; in round r it solves the subproblem and
+// part named by sched[r][s] (instance << 12 | block), or idles.  All blocks
+// of a subproblem sit in the same round, and every workgroup is resident,
+// so the workgroups a subproblem waits for are always running or will reach
+// it.  The launch tag comes from device memory (*epoch) and the last
+// workgroup to finish advances it, so a captured graph can replay the
+// launch; when the tag wraps, that workgroup clears every instance's
+// exchange words first.
+template <int TILES, int DLAG>
+__global__ __launch_bounds__(kThreads) void k_phase_batched(BatchLaunch b) {
+    __shared__ unsigned s_last;
+    const unsigned seq = *b.epoch;
+    for (int r = 0; r < b.rounds; ++r) {
+        const uint32_t e = b.sched[(size_t)r * gridDim.x + blockIdx.x];
+        if (e == 0xffffffffu) continue;
+        const PhaseArgs& a = b.args[e >> 12];
+        if (a.p <= 16) phase_body<1, TILES, DLAG>(a, e & 0xfffu, a.nblk, seq);
+        else phase_body<2, TILES, DLAG>(a, e & 0xfffu, a.nblk, seq);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned old = atomicAdd(b.done, 1u);
+        s_last = old == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last) {
+        const unsigned nx = seq + 1 < (1u << 22) ? seq + 1 : 1u;
+        if (nx == 1u) {
+            for (int i = 0; i < b.count; ++i) {
+                uint64_t* w = b.args[i].slot_s;
+                for (size_t k = threadIdx.x; k < kSlotWords; k += kThreads) w[k] = 0;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            *b.done = 0;
+            *b.epoch = nx;
+        }
+    }
+}
+
+template <int TILES>
+hipError_t launch_batched2(const Dev& d, const BatchLaunch& b, int dlag) {
+    dim3 grid((unsigned)b.slots), block(kThreads);
+    switch (dlag) {
+        case 0: hipLaunchKernelGGL((k_phase_batched<TILES, 0>), grid, block, 0, d.stream, b); break;
+        case 1: hipLaunchKernelGGL((k_phase_batched<TILES, 1>), grid, block, 0, d.stream, b); break;
+        case 2: hipLaunchKernelGGL((k_phase_batched<TILES, 2>), grid, block, 0, d.stream, b); break;
+        case 3: hipLaunchKernelGGL((k_phase_batched<TILES, 3>), grid, block, 0, d.stream, b); break;
+        default: hipLaunchKernelGGL((k_phase_batched<TILES, 4>), grid, block, 0, d.stream, b); break;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // Rows per workgroup and grid for `rows` rows: the grid must fit on the CUs
@@ -638,6 +701,15 @@ bool phase_grid(const Dev& d, int64_t rows, int* tiles, unsigned* nblk) {
         }
     }
     return false;
+}
+
+hipError_t phase_batched(const Dev& d, const BatchLaunch& b, int tiles, int dlag) {
+    if (dlag < 0 || dlag > 4 || b.slots < 1) return hipErrorInvalidValue;
+    switch (tiles) {
+        case 1: return launch_batched2<1>(d, b, dlag);
+        case 2: return launch_batched2<2>(d, b, dlag);
+        default: return launch_batched2<4>(d, b, dlag);
+    }
 }
 
 hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles) {
