@@ -71,6 +71,26 @@ struct cnmf_batch {
     size_t args_blocks = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // randomized subspace iteration (allocated on first use)
+    char* rmem = nullptr;
+    SweepDesc* rdesc = nullptr;         // right-sweep descriptors, (1 + 2q) x count
+    SweepDesc* ldesc = nullptr;         // left-sweep descriptors, (1 + 2q) x count
+    TransDesc* tdesc = nullptr;         // 2 x count
+    WorkItem* wr = nullptr;             // right sweep / reduce / left sweep / reduce / transposes
+    int64_t nwr = 0, nrr = 0, nwl = 0, nrl = 0, nwt = 0;
+    WorkItem *wrr = nullptr, *wl = nullptr, *wrl = nullptr, *wt = nullptr;
+    OrthArgs* oargs = nullptr;          // 4q arrays of `count`, one per orthonormalisation launch
+    uint32_t* osched_n = nullptr;       // round schedules of n-space and m-space panels
+    uint32_t* osched_m = nullptr;
+    int orounds_n = 0, orounds_m = 0;
+    std::vector<uint64_t*> oxw;         // per instance orthonormalisation exchange words
+    std::vector<size_t> oxw_words;
+    std::vector<unsigned> onb_n, onb_m; // workgroups per panel
+    struct RsiPtrs {
+        float *oRt, *Yn, *QL, *Ym, *QRt, *oLT, *QRtT, *QLtT, *pr, *pl;
+        int64_t ldt;
+    };
+    std::vector<RsiPtrs> rp;
 };
 
 namespace {
@@ -249,6 +269,167 @@ hipError_t enqueue(const cnmf_batch* b, const Dev& d, const PhaseArgs* args, int
     return hipSuccess;
 }
 
+// Panels of one orthonormalisation launch: workgroups per panel in
+// proportion to its rows so that all panels fit one round of `slots`.
+std::vector<unsigned> orth_share(const std::vector<int64_t>& rows, int slots) {
+    int64_t tot = 0;
+    for (int64_t r : rows) tot += r;
+    std::vector<unsigned> nb;
+    for (int64_t r : rows) {
+        int64_t v = (int64_t)((double)r * slots / (double)(tot > 0 ? tot : 1));
+        v = std::min<int64_t>(v, (int64_t)orth_batch_blocks(r));
+        nb.push_back((unsigned)std::max<int64_t>(1, v));
+    }
+    return nb;
+}
+
+// Workspace, descriptors, work lists and schedules of the batched RSI.
+int rsi_prepare(cnmf_batch* b) {
+    if (b->rmem) return CNMF_OK;
+    const int n = count_of(b);
+    const int q = b->prm.q;
+    for (const cnmf_instance& in : b->inst) {
+        if (!in.X || !in.omega_L || !in.omega_R) return CNMF_EINVAL;
+        if (in.ldx % 4 != 0 || (reinterpret_cast<uintptr_t>(in.X) & 15u)) return CNMF_EINVAL;
+    }
+    std::vector<int64_t> rn, rm;
+    for (const cnmf_instance& in : b->inst) {
+        rn.push_back(in.n);
+        rm.push_back(in.m);
+    }
+    b->onb_n = orth_share(rn, b->slots);
+    b->onb_m = orth_share(rm, b->slots);
+    Sched sn, sm;
+    if (!pack(b->onb_n, b->slots, &sn) || !pack(b->onb_m, b->slots, &sm)) return CNMF_EINVAL;
+    Arena ar;
+    struct Off { size_t oRt, Yn, QL, Ym, QRt, oLT, QRtT, QLtT, pr, pl, ox; int64_t ldt; };
+    std::vector<Off> off(n);
+    for (int i = 0; i < n; ++i) {
+        const cnmf_instance& in = b->inst[i];
+        const int l = in.p + in.nu;
+        const int64_t ldt = (in.m + 3) / 4 * 4;
+        Off& o = off[i];
+        o.ldt = ldt;
+        o.oRt = ar.take<float>((size_t)in.n * l);
+        o.Yn = ar.take<float>((size_t)in.n * l);
+        o.QL = ar.take<float>((size_t)in.n * l);
+        o.Ym = ar.take<float>((size_t)in.m * l);
+        o.QRt = ar.take<float>((size_t)in.m * l);
+        o.oLT = ar.take<float>((size_t)l * ldt);
+        o.QRtT = ar.take<float>((size_t)l * ldt);
+        o.QLtT = ar.take<float>((size_t)l * ldt);
+        o.pr = ar.take<float>((size_t)in.n * 32);
+        o.pl = ar.take<float>((size_t)in.m * 32);
+        const unsigned nb = std::max(b->onb_n[i], b->onb_m[i]);
+        b->oxw_words.push_back(orth_batch_exchange_words(nb));
+        o.ox = ar.take<uint64_t>(b->oxw_words.back());
+    }
+    const size_t nsteps = 1 + 2 * (size_t)q;
+    const size_t o_rd = ar.take<SweepDesc>(nsteps * n);
+    const size_t o_ld = ar.take<SweepDesc>(nsteps * n);
+    const size_t o_td = ar.take<TransDesc>(2 * (size_t)n);
+    const size_t o_oa = ar.take<OrthArgs>((size_t)4 * q * n);
+    // work lists
+    std::vector<WorkItem> wr, wrr, wl, wrl, wt;
+    std::vector<SweepDesc> rd(nsteps * n), ld(nsteps * n);
+    std::vector<TransDesc> td(2 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const cnmf_instance& in = b->inst[i];
+        const int l = in.p + in.nu;
+        const int nt = l <= 16 ? 16 : 32;
+        for (int t = 0; t < (int)((in.n + 31) / 32); ++t) wr.push_back({i, t});
+        for (int t = 0; t < (int)((in.m + 255) / 256); ++t) wl.push_back({i, t});
+        for (int t = 0; t < (int)((in.n * nt + 255) / 256); ++t) wrr.push_back({i, t});
+        for (int t = 0; t < (int)((in.m * nt + 255) / 256); ++t) wrl.push_back({i, t});
+        // transposes: Omega_R (l x n) -> n x l, Omega_L (m x l) -> l x ldt
+        const int64_t t0 = ((l + 31) / 32) * ((in.n + 31) / 32);
+        const int64_t t1 = ((in.m + 31) / 32) * ((l + 31) / 32);
+        for (int64_t t = 0; t < t0; ++t) wt.push_back({2 * i, (int)t});
+        for (int64_t t = 0; t < t1; ++t) wt.push_back({2 * i + 1, (int)t});
+    }
+    const size_t o_wr = ar.take<WorkItem>(wr.size());
+    const size_t o_wrr = ar.take<WorkItem>(wrr.size());
+    const size_t o_wl = ar.take<WorkItem>(wl.size());
+    const size_t o_wrl = ar.take<WorkItem>(wrl.size());
+    const size_t o_wt = ar.take<WorkItem>(wt.size());
+    const size_t o_sn = ar.take<uint32_t>(sn.cells.size());
+    const size_t o_sm = ar.take<uint32_t>(sm.cells.size());
+    if (hipMalloc((void**)&b->rmem, ar.off) != hipSuccess) {
+        b->rmem = nullptr;
+        return CNMF_ENOMEM;
+    }
+    char* base = b->rmem;
+    auto F = [&](size_t o) { return reinterpret_cast<float*>(base + o); };
+    for (int i = 0; i < n; ++i) {
+        const Off& o = off[i];
+        cnmf_batch::RsiPtrs r{F(o.oRt), F(o.Yn), F(o.QL), F(o.Ym), F(o.QRt), F(o.oLT),
+                              F(o.QRtT), F(o.QLtT), F(o.pr), F(o.pl), o.ldt};
+        b->rp.push_back(r);
+        b->oxw.push_back(reinterpret_cast<uint64_t*>(base + o.ox));
+    }
+    for (int i = 0; i < n; ++i) {
+        const cnmf_instance& in = b->inst[i];
+        const cnmf_batch::RsiPtrs& r = b->rp[i];
+        const int l = in.p + in.nu;
+        td[2 * i] = TransDesc{l, in.n, in.omega_R, in.n, r.oRt, l};
+        td[2 * i + 1] = TransDesc{in.m, l, in.omega_L, l, r.oLT, r.ldt};
+        // right sweeps: step 0 X oL, then per k: X Q_R^(k-1)^T... (as rsi_run)
+        size_t sr = 0, sl = 0;
+        auto R_ = [&](const float* AT, float* Y) {
+            sweep_desc_right(&rd[sr++ * n + i], in.n, in.m, in.X, in.ldx, l, AT, r.ldt, r.pr, Y, l);
+        };
+        auto L_ = [&](const float* B, float* Z, bool trans) {
+            sweep_desc_left(&ld[sl++ * n + i], in.n, in.m, in.X, in.ldx, l, B, l, r.pl, Z,
+                            trans ? in.m : l, trans);
+        };
+        R_(r.oLT, r.Yn);
+        L_(r.oRt, r.Ym, false);
+        for (int k = 1; k <= q; ++k) {
+            L_(r.QL, r.Ym, false);
+            R_(r.QRtT, r.Yn);
+            R_(r.QLtT, in.X_R);
+            if (k < q) L_(in.Q_L, r.Ym, false);
+            else L_(in.Q_L, in.X_L, true);
+        }
+    }
+    b->rdesc = reinterpret_cast<SweepDesc*>(base + o_rd);
+    b->ldesc = reinterpret_cast<SweepDesc*>(base + o_ld);
+    b->tdesc = reinterpret_cast<TransDesc*>(base + o_td);
+    b->oargs = reinterpret_cast<OrthArgs*>(base + o_oa);
+    b->wr = reinterpret_cast<WorkItem*>(base + o_wr);
+    b->wrr = reinterpret_cast<WorkItem*>(base + o_wrr);
+    b->wl = reinterpret_cast<WorkItem*>(base + o_wl);
+    b->wrl = reinterpret_cast<WorkItem*>(base + o_wrl);
+    b->wt = reinterpret_cast<WorkItem*>(base + o_wt);
+    b->osched_n = reinterpret_cast<uint32_t*>(base + o_sn);
+    b->osched_m = reinterpret_cast<uint32_t*>(base + o_sm);
+    b->nwr = (int64_t)wr.size();
+    b->nrr = (int64_t)wrr.size();
+    b->nwl = (int64_t)wl.size();
+    b->nrl = (int64_t)wrl.size();
+    b->nwt = (int64_t)wt.size();
+    b->orounds_n = sn.rounds;
+    b->orounds_m = sm.rounds;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        return bytes == 0 || hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up(b->rdesc, rd.data(), rd.size() * sizeof(SweepDesc)) ||
+        !up(b->ldesc, ld.data(), ld.size() * sizeof(SweepDesc)) ||
+        !up(b->tdesc, td.data(), td.size() * sizeof(TransDesc)) ||
+        !up(b->wr, wr.data(), wr.size() * sizeof(WorkItem)) ||
+        !up(b->wrr, wrr.data(), wrr.size() * sizeof(WorkItem)) ||
+        !up(b->wl, wl.data(), wl.size() * sizeof(WorkItem)) ||
+        !up(b->wrl, wrl.data(), wrl.size() * sizeof(WorkItem)) ||
+        !up(b->wt, wt.data(), wt.size() * sizeof(WorkItem)) ||
+        !up(b->osched_n, sn.cells.data(), sn.cells.size() * 4) ||
+        !up(b->osched_m, sm.cells.data(), sm.cells.size() * 4))
+        return CNMF_EHIP;
+    for (int i = 0; i < n; ++i)
+        if (fill_u64(b->c->dev, b->oxw[i], (int64_t)b->oxw_words[i], 0) != hipSuccess)
+            return CNMF_EHIP;
+    return CNMF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -330,6 +511,7 @@ int cnmf_batch_destroy(cnmf_batch* b) {
     if (b->c) (void)hipSetDevice(b->c->dev.device);
     if (b->c) (void)hipStreamSynchronize(b->c->dev.stream);
     free_plan(b);
+    if (b->rmem) (void)hipFree(b->rmem);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->mem) (void)hipFree(b->mem);
     delete b;
@@ -338,14 +520,93 @@ int cnmf_batch_destroy(cnmf_batch* b) {
 
 int cnmf_batch_rsi(cnmf_batch* b) {
     if (!b) return CNMF_EINVAL;
-    for (const cnmf_instance& in : b->inst) {
-        if (!in.X || !in.omega_L || !in.omega_R) return CNMF_EINVAL;
-        cnmf_params pi = b->prm;
-        pi.p = in.p;
-        pi.nu = in.nu;
-        const int rc = rsi_run(b->c, in.n, in.m, in.X, nullptr, in.ldx, &pi, in.omega_L,
-                               in.omega_R, in.Q_L, in.Q_R, in.X_L, in.X_R);
-        if (rc) return rc;
+    cnmf_ctx* c = b->c;
+    if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
+    const int rc = rsi_prepare(b);
+    if (rc) return rc;
+    const Dev& d = c->dev;
+    const int n = count_of(b);
+    const int q = b->prm.q;
+    // fresh tags for the 2 + 3q - 1 orthonormalisation launches
+    const int north = 4 * q;
+    std::vector<OrthArgs> oa((size_t)north * n);
+    std::vector<unsigned> seqs(north);
+    bool wrapped = false;
+    for (int j = 0; j < north; ++j) {
+        const unsigned before = c->seq;
+        if (next_seq(c, &seqs[j]) != hipSuccess) return CNMF_EHIP;
+        if (seqs[j] < before) wrapped = true;
+    }
+    if (wrapped)
+        for (int i = 0; i < n; ++i)
+            CK(fill_u64(d, b->oxw[i], (int64_t)b->oxw_words[i], 0));
+    // orth launch j: panels of every instance (n-space or m-space)
+    auto set_orth = [&](int j, int i, bool nspace, const float* Y, float* Q, float* QT) {
+        const cnmf_instance& in = b->inst[i];
+        const cnmf_batch::RsiPtrs& r = b->rp[i];
+        const int l = in.p + in.nu;
+        oa[(size_t)j * n + i] =
+            nspace ? orth_args(in.n, l, Y, r.oRt, false, b->prm.tau2, Q, nullptr, 0, nullptr,
+                               b->oxw[i], seqs[j], c->ctl, b->onb_n[i])
+                   : orth_args(in.m, l, Y, in.omega_L, false, b->prm.tau2, Q, QT, r.ldt,
+                               nullptr, b->oxw[i], seqs[j], c->ctl, b->onb_m[i]);
+    };
+    // the orthonormalisation sequence of Algorithm 2 (see rsi_run)
+    int j = 0;
+    std::vector<std::pair<int, bool>> order;   // (launch, n-space)
+    for (int i = 0; i < n; ++i) {
+        const cnmf_instance& in = b->inst[i];
+        const cnmf_batch::RsiPtrs& r = b->rp[i];
+        int jj = 0;
+        set_orth(jj++, i, true, r.Yn, r.QL, nullptr);
+        set_orth(jj++, i, false, r.Ym, r.QRt, r.QRtT);
+        for (int k = 1; k <= q; ++k) {
+            set_orth(jj++, i, false, r.Ym, in.Q_R, r.QLtT);
+            set_orth(jj++, i, true, r.Yn, in.Q_L, nullptr);
+            if (k < q) {
+                set_orth(jj++, i, true, in.X_R, r.QL, nullptr);
+                set_orth(jj++, i, false, r.Ym, r.QRt, r.QRtT);
+            }
+        }
+        j = jj;
+    }
+    const int used = j;
+    CK(hipMemcpyAsync(b->oargs, oa.data(), (size_t)used * n * sizeof(OrthArgs),
+                      hipMemcpyHostToDevice, d.stream));
+    CK(hipStreamSynchronize(d.stream));   // oa is pageable host memory
+    auto orth_launch = [&](int jl, bool nspace) -> hipError_t {
+        return orth_batched(d, b->oargs + (size_t)jl * n, nspace ? b->osched_n : b->osched_m,
+                            nspace ? b->orounds_n : b->orounds_m, b->slots);
+    };
+    auto right = [&](int step) -> hipError_t {
+        const SweepDesc* s = b->rdesc + (size_t)step * n;
+        hipError_t e = sweep_right_batched(d, s, b->wr, b->nwr);
+        if (e != hipSuccess) return e;
+        return reduce_batched(d, s, b->wrr, b->nrr, false);
+    };
+    auto left = [&](int step) -> hipError_t {
+        const SweepDesc* s = b->ldesc + (size_t)step * n;
+        hipError_t e = sweep_left_batched(d, s, b->wl, b->nwl);
+        if (e != hipSuccess) return e;
+        return reduce_batched(d, s, b->wrl, b->nrl, true);
+    };
+    CK(transpose_batched(d, b->tdesc, b->wt, b->nwt));
+    int jo = 0, sr = 0, sl = 0;
+    CK(right(sr++));
+    CK(orth_launch(jo++, true));
+    CK(left(sl++));
+    CK(orth_launch(jo++, false));
+    for (int k = 1; k <= q; ++k) {
+        CK(left(sl++));
+        CK(orth_launch(jo++, false));
+        CK(right(sr++));
+        CK(orth_launch(jo++, true));
+        CK(right(sr++));
+        CK(left(sl++));
+        if (k < q) {
+            CK(orth_launch(jo++, true));
+            CK(orth_launch(jo++, false));
+        }
     }
     return CNMF_OK;
 }

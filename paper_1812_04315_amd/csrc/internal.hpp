@@ -155,6 +155,50 @@ size_t sweep_left_partial_floats(const Dev& d, int64_t R, int64_t C);
 hipError_t sweep_left(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx,
                       int k, const float* B, int64_t ldb, float* Z, int64_t ldz,
                       bool z_trans, float* partial);
+// Batched sweeps: one descriptor per instance; work items {instance, item}
+// with item = slice * tiles + tile (sweeps), a 256-element chunk of the
+// slice reduction, or a 32 x 32 transpose tile.  X rows and the skinny
+// operands must allow 16-byte vector loads (row pitches multiple of 4).
+struct SweepDesc {
+    int64_t R, C;          // X is R x C
+    const float* X;
+    int64_t ldx;
+    int k, nt;             // columns of the skinny operand, MFMA tile width (16 / 32)
+    const float* A;        // right: A^T (k x C, lda); left: B (R x k, lda)
+    int64_t lda;
+    float* partial;        // [S][rows][nt], rows = R (right) or C (left)
+    int64_t span;          // right: columns per slice; left: rows per slice
+    int tiles, S;
+    float* Y;              // reduction output (rows x k, or k x rows when trans)
+    int64_t ldy;
+    int trans;
+};
+struct WorkItem {
+    int inst, item;
+};
+// Plans: tiles and slices for one instance (S = 1 unless `slices` > 1).
+void sweep_desc_right(SweepDesc* s, int64_t R, int64_t C, const float* X, int64_t ldx, int k,
+                      const float* AT, int64_t ldt, float* partial, float* Y, int64_t ldy);
+void sweep_desc_left(SweepDesc* s, int64_t R, int64_t C, const float* X, int64_t ldx, int k,
+                     const float* B, int64_t ldb, float* partial, float* Y, int64_t ldy,
+                     bool trans);
+hipError_t sweep_right_batched(const Dev& d, const SweepDesc* desc, const WorkItem* work,
+                               int64_t nwork);
+hipError_t sweep_left_batched(const Dev& d, const SweepDesc* desc, const WorkItem* work,
+                              int64_t nwork);
+hipError_t reduce_batched(const Dev& d, const SweepDesc* desc, const WorkItem* work,
+                          int64_t nwork, bool left);
+// out (B: C x R, ldb) = A^T for every descriptor {R, C, A, lda, B, ldb}.
+struct TransDesc {
+    int64_t R, C;
+    const float* A;
+    int64_t lda;
+    float* B;
+    int64_t ldb;
+};
+hipError_t transpose_batched(const Dev& d, const TransDesc* desc, const WorkItem* work,
+                             int64_t nwork);
+
 // reduce_slices: out (rows x k, or k x rows if trans) = sum of S partial
 // slices [S][rows][nt] in slice order (bitwise reproducible).
 hipError_t reduce_slices(const Dev& d, int64_t rows, int k, int64_t S, int nt,
@@ -192,6 +236,38 @@ hipError_t check_input(const Dev& d, int64_t R, int64_t C, const float* X, int64
 // words (orth_exchange_words()); seq: launch tag (< 2^22), fresh per call.
 // QT (optional): transposed copy of Q with row pitch ldqt.
 size_t orth_exchange_words();
+
+constexpr int kOrthMaxPairs = 64 * 65 / 2;   // entries of the largest (augmented) Gram
+// Arguments of one panel's orthonormalisation (batched launches keep an
+// array of them on the device).
+struct OrthArgs {
+    int64_t N;
+    int l;
+    const float* Y;
+    const float* P;
+    int64_t p_rs, p_cs;
+    double tau2;
+    float* Q;           // N x l
+    float* QT;          // optional l x N copy, row pitch ldqt
+    int64_t ldqt;
+    int32_t* replaced;  // optional l flags
+    uint64_t* part;     // [nblk][kMaxPairs][2]
+    uint64_t* red;      // [kMaxPairs][2]
+    unsigned seq;
+    Control* ctl;
+    unsigned nblk;      // batched launches: workgroups of this panel
+};
+
+// Batched orthonormalisation: exchange words per panel, workgroups per
+// panel, argument helper and the launch over a round schedule (as for the
+// batched subproblems).
+size_t orth_batch_exchange_words(unsigned nblk);
+unsigned orth_batch_blocks(int64_t N);
+OrthArgs orth_args(int64_t N, int l, const float* Y, const float* pool, bool pool_trans,
+                   double tau2, float* Q, float* QT, int64_t ldqt, int32_t* replaced,
+                   uint64_t* xch, unsigned seq, Control* ctl, unsigned nblk);
+hipError_t orth_batched(const Dev& d, const OrthArgs* args, const uint32_t* sched, int rounds,
+                        int slots);
 hipError_t orth(const Dev& d, int64_t N, int l, const float* Y, const float* pool,
                 bool pool_trans, double tau2, float* Q, float* QT, int64_t ldqt,
                 int32_t* replaced, uint64_t* xch, unsigned seq, Control* ctl);

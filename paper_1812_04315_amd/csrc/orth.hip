@@ -33,7 +33,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxW = 64;        // augmented width 2 l
-constexpr int kMaxPairs = kMaxW * (kMaxW + 1) / 2;   // 2080
+constexpr int kMaxPairs = kOrthMaxPairs;   // pairs of a 64-column Gram
 constexpr int kPairsPerThread = (kMaxPairs + kThreads - 1) / kThreads;   // 9
 constexpr int kTile = 32;
 
@@ -77,22 +77,6 @@ struct Shared {
 
 }  // namespace
 
-struct OrthArgs {
-    int64_t N;
-    int l;
-    const float* Y;
-    const float* P;
-    int64_t p_rs, p_cs;
-    double tau2;
-    float* Q;           // N x l
-    float* QT;          // optional l x N copy, row pitch ldqt
-    int64_t ldqt;
-    int32_t* replaced;  // optional l flags
-    uint64_t* part;     // [nblk][kMaxPairs][2]
-    uint64_t* red;      // [kMaxPairs][2]
-    unsigned seq;
-    Control* ctl;
-};
 
 namespace {
 
@@ -138,20 +122,20 @@ __device__ void gram_partial(const OrthArgs& g, Shared& sh, const float* A, int 
 // Returns false on a stalled exchange.
 __device__ bool gram_exchange(const OrthArgs& g, Shared& sh, int w, unsigned tag_part,
                               unsigned tag_red, const double (&acc)[kPairsPerThread],
-                              const int (&pa)[kPairsPerThread], const int (&pb)[kPairsPerThread]) {
+                              const int (&pa)[kPairsPerThread], const int (&pb)[kPairsPerThread],
+                              const unsigned blk, const unsigned nblk) {
     const int npairs = w * (w + 1) / 2;
-    const unsigned nblk = gridDim.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // 1. publish this workgroup's partial
 #pragma unroll
     for (int s = 0; s < kPairsPerThread; ++s) {
         const int e = threadIdx.x + s * kThreads;
-        if (e < npairs) xstore(g.part + ((size_t)blockIdx.x * kMaxPairs + e) * 2, tag_part, acc[s]);
+        if (e < npairs) xstore(g.part + ((size_t)blk * kMaxPairs + e) * 2, tag_part, acc[s]);
     }
     // 2. reduce a share of the entries over all partials, one wave per entry
     if (threadIdx.x == 0) sh.timeout = 0;
     __syncthreads();
-    for (int e = blockIdx.x + nblk * wave; e < npairs; e += nblk * 4) {
+    for (int e = (int)blk + (int)nblk * wave; e < npairs; e += (int)nblk * 4) {
         unsigned spins = 0;
         double t;
         for (;;) {
@@ -406,11 +390,12 @@ __device__ void apply_rows(const OrthArgs& g, Shared& sh, const float* Ysrc, boo
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_orth(OrthArgs g) {
+__device__ __forceinline__ void orth_body(const OrthArgs& g, const unsigned blk,
+                                          const unsigned nblk) {
     __shared__ Shared sh;
-    const unsigned nblk = gridDim.x;
+    __syncthreads();   // LDS of a previous panel on this workgroup
     const int64_t rpw = (g.N + nblk - 1) / nblk;
-    const int64_t r0 = (int64_t)blockIdx.x * rpw;
+    const int64_t r0 = (int64_t)blk * rpw;
     const int64_t r1 = min(g.N, r0 + rpw);
     const int l = g.l;
     double acc[kPairsPerThread];
@@ -430,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_orth(OrthArgs g) {
         const float* A = stage == 2 ? g.Q : g.Y;
         const unsigned tag = (g.seq << 10) | (unsigned)(2 * stage + 1);
         gram_partial(g, sh, A, w, r0, r1, acc, pa, pb);
-        if (!gram_exchange(g, sh, w, tag, tag + 1, acc, pa, pb)) return;
+        if (!gram_exchange(g, sh, w, tag, tag + 1, acc, pa, pb, blk, nblk)) return;
         if (threadIdx.x < 64) {
             if (aug) cholesky_wave(g, sh, w, true);
             else cholesky_regs(g, sh, stage == 0);
@@ -440,11 +425,29 @@ __global__ __launch_bounds__(kThreads) void k_orth(OrthArgs g) {
             stage = 1;
             continue;
         }
-        if (stage < 2 && blockIdx.x == 0 && g.replaced && threadIdx.x < l)
+        if (stage < 2 && blk == 0 && g.replaced && threadIdx.x < l)
             g.replaced[threadIdx.x] = sh.sel[threadIdx.x];
         apply_rows(g, sh, A, stage < 2, r0, r1, g.Q, stage == 2 ? g.QT : nullptr);
         __syncthreads();
         stage = stage < 2 ? 2 : 3;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_orth(OrthArgs g) {
+    orth_body(g, blockIdx.x, gridDim.x);
+}
+
+// Batched: workgroup s walks the rounds of sched (instance << 12 | block or
+// 0xffffffff); all blocks of a panel share a round and every workgroup is
+// resident (the same argument as for the batched subproblem kernel).
+__global__ __launch_bounds__(kThreads) void k_orth_batched(const OrthArgs* __restrict__ args,
+                                                          const uint32_t* __restrict__ sched,
+                                                          int rounds) {
+    for (int r = 0; r < rounds; ++r) {
+        const uint32_t e = sched[(size_t)r * gridDim.x + blockIdx.x];
+        if (e == 0xffffffffu) continue;
+        const OrthArgs& g = args[e >> 12];
+        orth_body(g, e & 0xfffu, g.nblk);
     }
 }
 
@@ -459,12 +462,17 @@ unsigned orth_blocks(const Dev& d, int64_t N) {
 
 size_t orth_exchange_words() { return (size_t)257 * kMaxPairs * 2; }
 
-hipError_t orth(const Dev& d, int64_t N, int l, const float* Y, const float* pool,
-                bool pool_trans, double tau2, float* Q, float* QT, int64_t ldqt,
-                int32_t* replaced, uint64_t* xch, unsigned seq, Control* ctl) {
-    if (N <= 0 || l <= 0) return hipSuccess;
-    if (l > 32 || seq >= (1u << 22)) return hipErrorInvalidValue;
-    OrthArgs g;
+size_t orth_batch_exchange_words(unsigned nblk) { return (size_t)(nblk + 1) * kMaxPairs * 2; }
+
+unsigned orth_batch_blocks(int64_t N) {
+    const int64_t b = (N + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > 256 ? 256 : b));
+}
+
+OrthArgs orth_args(int64_t N, int l, const float* Y, const float* pool, bool pool_trans,
+                   double tau2, float* Q, float* QT, int64_t ldqt, int32_t* replaced,
+                   uint64_t* xch, unsigned seq, Control* ctl, unsigned nblk) {
+    OrthArgs g{};
     g.N = N;
     g.l = l;
     g.Y = Y;
@@ -480,7 +488,27 @@ hipError_t orth(const Dev& d, int64_t N, int l, const float* Y, const float* poo
     g.red = xch;
     g.seq = seq;
     g.ctl = ctl;
-    hipLaunchKernelGGL(k_orth, dim3(orth_blocks(d, N)), dim3(kThreads), 0, d.stream, g);
+    g.nblk = nblk;
+    return g;
+}
+
+hipError_t orth_batched(const Dev& d, const OrthArgs* args, const uint32_t* sched, int rounds,
+                        int slots) {
+    if (rounds < 1 || slots < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_orth_batched, dim3((unsigned)slots), dim3(kThreads), 0, d.stream, args,
+                       sched, rounds);
+    return hipGetLastError();
+}
+
+hipError_t orth(const Dev& d, int64_t N, int l, const float* Y, const float* pool,
+                bool pool_trans, double tau2, float* Q, float* QT, int64_t ldqt,
+                int32_t* replaced, uint64_t* xch, unsigned seq, Control* ctl) {
+    if (N <= 0 || l <= 0) return hipSuccess;
+    if (l > 32 || seq >= (1u << 22)) return hipErrorInvalidValue;
+    const unsigned nb = orth_blocks(d, N);
+    const OrthArgs g = orth_args(N, l, Y, pool, pool_trans, tau2, Q, QT, ldqt, replaced, xch, seq,
+                                 ctl, nb);
+    hipLaunchKernelGGL(k_orth, dim3(nb), dim3(kThreads), 0, d.stream, g);
     return hipGetLastError();
 }
 

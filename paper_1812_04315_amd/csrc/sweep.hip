@@ -83,17 +83,17 @@ __device__ __forceinline__ void right_load_a(const float* __restrict__ A, int64_
 }
 
 template <int NT, int SW, bool A_T, bool DIRECT, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_sweep_right(
+__device__ __forceinline__ void right_body(
     int64_t R, int64_t C, const float* __restrict__ X, int64_t ldx, int k,
     const float* __restrict__ A, int64_t lda, float* __restrict__ out, int64_t ldo,
-    int64_t span) {
+    int64_t span, const int64_t tile, const int64_t slice) {
     using Sh = RightShape<NT, SW>;
     constexpr int KW = Sh::KW, NA = Sh::NA, PITCH = Sh::PITCH, XV = Sh::XV;
     __shared__ __attribute__((aligned(16))) float xs[32 * PITCH > 4096 ? 32 * PITCH : 4096];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * 32;
-    const int64_t c_lo = (int64_t)blockIdx.y * span;
+    const int64_t row0 = tile * 32;
+    const int64_t c_lo = slice * span;
     const int64_t c_hi = min(C, c_lo + span);
     const int64_t nst = (c_hi - c_lo + SW - 1) / SW;
     const int koff = KW * wave + NA * (NT == 32 ? (lane >> 5) : (lane >> 4));
@@ -235,10 +235,19 @@ __global__ __launch_bounds__(kThreads) void k_sweep_right(
             if (DIRECT) {
                 if (col < k) out[row * ldo + col] = s;
             } else {
-                out[((int64_t)blockIdx.y * R + row) * NT + col] = s;
+                out[(slice * R + row) * NT + col] = s;
             }
         }
     }
+}
+
+template <int NT, int SW, bool A_T, bool DIRECT, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_sweep_right(
+    int64_t R, int64_t C, const float* __restrict__ X, int64_t ldx, int k,
+    const float* __restrict__ A, int64_t lda, float* __restrict__ out, int64_t ldo,
+    int64_t span) {
+    right_body<NT, SW, A_T, DIRECT, VEC>(R, C, X, ldx, k, A, lda, out, ldo, span, blockIdx.x,
+                                         blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -255,16 +264,17 @@ __global__ __launch_bounds__(kThreads) void k_sweep_right(
 constexpr int kLPad = 272;   // row pitch: 4-row groups of 16 floats hit distinct banks
 
 template <int NT, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_sweep_left(
+__device__ __forceinline__ void left_body(
     int64_t R, int64_t C, const float* __restrict__ X, int64_t ldx, int k,
-    const float* __restrict__ B, int64_t ldb, float* __restrict__ partial, int64_t rspan) {
+    const float* __restrict__ B, int64_t ldb, float* __restrict__ partial, int64_t rspan,
+    const int64_t tile, const int64_t slice) {
     __shared__ __attribute__((aligned(16))) float xs[16 * kLPad];
     constexpr int KS = NT == 32 ? 8 : 4;        // K steps per stage
     constexpr int MT = NT == 32 ? 2 : 4;        // M tiles per wave
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t col0 = (int64_t)blockIdx.x * 256;
-    const int64_t r_lo = (int64_t)blockIdx.y * rspan;
+    const int64_t col0 = tile * 256;
+    const int64_t r_lo = slice * rspan;
     const int64_t r_hi = min(R, r_lo + rspan);
     const int64_t nst = (r_hi - r_lo + 15) / 16;
     const int n = NT == 32 ? (lane & 31) : (lane & 15);
@@ -370,16 +380,23 @@ __global__ __launch_bounds__(kThreads) void k_sweep_left(
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t c = col0 + 64 * wave + 32 * t + acc_row(r, lane);
-                if (c < C) partial[((int64_t)blockIdx.y * C + c) * NT + (lane & 31)] = acc32[t][r];
+                if (c < C) partial[(slice * C + c) * NT + (lane & 31)] = acc32[t][r];
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int64_t c = col0 + 64 * wave + 16 * t + 4 * (lane >> 4) + i;
-                if (c < C) partial[((int64_t)blockIdx.y * C + c) * NT + (lane & 15)] = acc16[t][i];
+                if (c < C) partial[(slice * C + c) * NT + (lane & 15)] = acc16[t][i];
             }
         }
     }
+}
+
+template <int NT, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_sweep_left(
+    int64_t R, int64_t C, const float* __restrict__ X, int64_t ldx, int k,
+    const float* __restrict__ B, int64_t ldb, float* __restrict__ partial, int64_t rspan) {
+    left_body<NT, VEC>(R, C, X, ldx, k, B, ldb, partial, rspan, blockIdx.x, blockIdx.y);
 }
 
 // out (rows x k) = sum over S slices of partial[s][rows][nt]; optionally
@@ -455,6 +472,70 @@ LeftPlan left_plan(const Dev& d, int64_t R, int64_t C, int k) {
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// ---------------------------------------------------------------------------
+// Batched launches: one workgroup per work item, any mix of instances.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_sweep_right_batched(const SweepDesc* __restrict__ desc,
+                                                                 const WorkItem* __restrict__ work) {
+    const WorkItem w = work[blockIdx.x];
+    const SweepDesc& s = desc[w.inst];
+    const int64_t tile = w.item % s.tiles, slice = w.item / s.tiles;
+    if (s.nt == 16)
+        right_body<16, 128, true, false, true>(s.R, s.C, s.X, s.ldx, s.k, s.A, s.lda, s.partial,
+                                               16, s.span, tile, slice);
+    else
+        right_body<32, 128, true, false, true>(s.R, s.C, s.X, s.ldx, s.k, s.A, s.lda, s.partial,
+                                               32, s.span, tile, slice);
+}
+
+__global__ __launch_bounds__(kThreads) void k_sweep_left_batched(const SweepDesc* __restrict__ desc,
+                                                                const WorkItem* __restrict__ work) {
+    const WorkItem w = work[blockIdx.x];
+    const SweepDesc& s = desc[w.inst];
+    const int64_t tile = w.item % s.tiles, slice = w.item / s.tiles;
+    if (s.nt == 16)
+        left_body<16, true>(s.R, s.C, s.X, s.ldx, s.k, s.A, s.lda, s.partial, s.span, tile, slice);
+    else
+        left_body<32, true>(s.R, s.C, s.X, s.ldx, s.k, s.A, s.lda, s.partial, s.span, tile, slice);
+}
+
+// Slice sums of one 256-element chunk of an instance's partial output.
+__global__ __launch_bounds__(kThreads) void k_reduce_batched(const SweepDesc* __restrict__ desc,
+                                                            const WorkItem* __restrict__ work,
+                                                            int left) {
+    const WorkItem w = work[blockIdx.x];
+    const SweepDesc& s = desc[w.inst];
+    const int64_t rows = left ? s.C : s.R;
+    const int64_t e = (int64_t)w.item * kThreads + threadIdx.x;
+    if (e >= rows * s.nt) return;
+    const int64_t r = e / s.nt;
+    const int c = (int)(e % s.nt);
+    if (c >= s.k) return;
+    float v = 0.f;
+    for (int i = 0; i < s.S; ++i) v += s.partial[((int64_t)i * rows + r) * s.nt + c];
+    if (s.trans) s.Y[(int64_t)c * s.ldy + r] = v;
+    else s.Y[r * s.ldy + c] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_transpose_batched(const TransDesc* __restrict__ desc,
+                                                               const WorkItem* __restrict__ work) {
+    __shared__ float tile[32][33];
+    const WorkItem w = work[blockIdx.x];
+    const TransDesc& t = desc[w.inst];
+    const int64_t tc = (t.C + 31) / 32;
+    const int64_t r0 = (w.item / tc) * 32, c0 = (w.item % tc) * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int j = ty; j < 32; j += 8) {
+        const int64_t r = r0 + j, c = c0 + tx;
+        tile[j][tx] = (r < t.R && c < t.C) ? t.A[r * t.lda + c] : 0.f;
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+        const int64_t c = c0 + j, r = r0 + tx;
+        if (c < t.C && r < t.R) t.B[c * t.ldb + r] = tile[tx][j];
+    }
+}
 
 }  // namespace
 
@@ -602,6 +683,83 @@ hipError_t to_bf16(const Dev& d, int64_t R, int64_t C, const float* X, int64_t l
     if (R <= 0 || C <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)(8 * d.num_cus)), dim3(kThreads), 0, d.stream,
                        R, C, X, ldx, Xb, ldxb);
+    return hipGetLastError();
+}
+
+}  // namespace cnmf
+
+namespace cnmf {
+
+void sweep_desc_right(SweepDesc* s, int64_t R, int64_t C, const float* X, int64_t ldx, int k,
+                      const float* AT, int64_t ldt, float* partial, float* Y, int64_t ldy) {
+    *s = SweepDesc{};
+    s->R = R;
+    s->C = C;
+    s->X = X;
+    s->ldx = ldx;
+    s->k = k;
+    s->nt = k <= 16 ? 16 : 32;
+    s->A = AT;
+    s->lda = ldt;
+    s->partial = partial;
+    s->tiles = (int)((R + 31) / 32);
+    s->S = 1;
+    s->span = (C + 127) / 128 * 128;
+    s->Y = Y;
+    s->ldy = ldy;
+    s->trans = 0;
+}
+
+void sweep_desc_left(SweepDesc* s, int64_t R, int64_t C, const float* X, int64_t ldx, int k,
+                     const float* B, int64_t ldb, float* partial, float* Y, int64_t ldy,
+                     bool trans) {
+    *s = SweepDesc{};
+    s->R = R;
+    s->C = C;
+    s->X = X;
+    s->ldx = ldx;
+    s->k = k;
+    s->nt = k <= 16 ? 16 : 32;
+    s->A = B;
+    s->lda = ldb;
+    s->partial = partial;
+    s->tiles = (int)((C + 255) / 256);
+    s->S = 1;
+    s->span = (R + 15) / 16 * 16;
+    s->Y = Y;
+    s->ldy = ldy;
+    s->trans = trans ? 1 : 0;
+}
+
+hipError_t sweep_right_batched(const Dev& d, const SweepDesc* desc, const WorkItem* work,
+                               int64_t nwork) {
+    if (nwork <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sweep_right_batched, dim3((unsigned)nwork), dim3(kThreads), 0, d.stream,
+                       desc, work);
+    return hipGetLastError();
+}
+
+hipError_t sweep_left_batched(const Dev& d, const SweepDesc* desc, const WorkItem* work,
+                              int64_t nwork) {
+    if (nwork <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sweep_left_batched, dim3((unsigned)nwork), dim3(kThreads), 0, d.stream,
+                       desc, work);
+    return hipGetLastError();
+}
+
+hipError_t reduce_batched(const Dev& d, const SweepDesc* desc, const WorkItem* work,
+                          int64_t nwork, bool left) {
+    if (nwork <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_batched, dim3((unsigned)nwork), dim3(kThreads), 0, d.stream,
+                       desc, work, left ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t transpose_batched(const Dev& d, const TransDesc* desc, const WorkItem* work,
+                             int64_t nwork) {
+    if (nwork <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_transpose_batched, dim3((unsigned)nwork), dim3(kThreads), 0, d.stream,
+                       desc, work);
     return hipGetLastError();
 }
 

@@ -134,15 +134,27 @@ def test_batch_rsi_and_tune():
         comp = (torch.empty(n, ell, device="cuda"), torch.empty(m, ell, device="cuda"),
                 torch.empty(ell, m, device="cuda"), torch.empty(n, ell, device="cuda"))
         d = _desc(inst, comp, T)
-        d.update(X=dev(inst.X), omega_L=dev(inst.omega_L), omega_R=dev(inst.omega_R))
+        d.update(X=dev(inst.X, (m + 3) // 4 * 4), omega_L=dev(inst.omega_L),
+                 omega_R=dev(inst.omega_R))
         descs.append(d)
     b = cnmf.Batch(descs, q=2, outer_iters=T, inner_max=K)
     b.rsi()
     cnmf.check()
     for d, inst in zip(descs, insts):
-        single = cnmf.rsi(d["X"], d["omega_L"], d["omega_R"], inst.p, inst.ell - inst.p, 2)
-        for a, s in zip((d["Q_L"], d["Q_R"], d["X_L"], d["X_R"]), single):
-            assert np.array_equal(host(a), host(s))
+        # noisy data: compare what is range-invariant (signal projector,
+        # compressed reconstruction error) with the oracle
+        ref = oracle.rsi(inst.X, inst.omega_L, inst.omega_R, 2)
+        QL, QR, XL = host(d["Q_L"]), host(d["Q_R"]), host(d["X_L"])
+        ell = inst.ell
+        for Q in (QL, QR):
+            assert np.linalg.norm(Q.T @ Q - np.eye(ell)) <= 1e-5
+        Xh = inst.X.astype(np.float64)
+        U, s, Vt = np.linalg.svd(Xh, full_matrices=False)
+        for Q, Qo, S in ((QL, ref.Q_L, U[:, :inst.p]), (QR, ref.Q_R, Vt[:inst.p].T)):
+            assert rel_fro(Q @ (Q.T @ S), Qo @ (Qo.T @ S)) <= PARITY_RTOL
+        e_gpu = np.linalg.norm(Xh - QL @ XL) / np.linalg.norm(Xh)
+        e_ref = np.linalg.norm(Xh - ref.Q_L @ ref.X_L) / np.linalg.norm(Xh)
+        assert abs(e_gpu - e_ref) <= 1e-3 * e_ref
     tg, tf = b.tune(2)
     assert tg in (1, 2, 4) and tf in (1, 2, 4)
     # the tuned schedule solves the same problems: replay the oracle's counts
@@ -177,3 +189,31 @@ def test_batch_rejects_bad_descriptors():
     d["nu"] = 2
     with pytest.raises(cnmf.CnmfError):
         cnmf.Batch([d], outer_iters=2, tiles_g=3)
+
+
+def test_batch_rsi_noiseless_bases_match_oracle():
+    """Exactly low-rank instances of uneven shapes: every basis column is
+    fixed (deficient columns come from the other Gaussian draw), so the
+    batched bases and compressed data match the oracle entry by entry."""
+    say("batch_rsi_exact")
+    import torch
+    shapes = [(200, 150, 5, 10), (97, 131, 3, 6), (300, 41, 7, 9), (500, 420, 12, 10)]
+    insts = [synth.instance(n, m, p, nu, seed=70 + k) for k, (n, m, p, nu) in enumerate(shapes)]
+    descs = []
+    for inst in insts:
+        n, m = inst.X.shape
+        ell = inst.ell
+        ld = (m + 3) // 4 * 4
+        comp = (torch.empty(n, ell, device="cuda"), torch.empty(m, ell, device="cuda"),
+                torch.empty(ell, m, device="cuda"), torch.empty(n, ell, device="cuda"))
+        d = _desc(inst, comp, 2)
+        d.update(X=dev(inst.X, ld), omega_L=dev(inst.omega_L), omega_R=dev(inst.omega_R))
+        descs.append(d)
+    b = cnmf.Batch(descs, q=4, outer_iters=2, inner_max=10)
+    b.rsi()
+    cnmf.check()
+    for d, inst in zip(descs, insts):
+        ref = oracle.rsi(inst.X, inst.omega_L, inst.omega_R, 4)
+        for key, r in (("Q_L", ref.Q_L), ("Q_R", ref.Q_R), ("X_L", ref.X_L), ("X_R", ref.X_R)):
+            assert rel_fro(host(d[key]), r) <= PARITY_RTOL, key
+    b.close()
