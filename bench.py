@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle sample on the host (0 disables)")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--form", choices=["headline", "bf16", "batched"], default="headline",
+                    help="headline: compressed vs plain on the 10k x 10k instance; bf16: the "
+                         "precision form on 20000 x 8000; batched: 256 uneven instances")
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the dominant sweep (and an X-sized device copy as the "
                          "counter reference) for hardware-counter runs")
@@ -147,6 +150,100 @@ def kernel_only(args, cnmf, torch, X, F):
                       "reference_copy_bytes_each_way": X.shape[0] * X.shape[1] * 4}), flush=True)
 
 
+def bench_batched(args, torch, cnmf, synth):
+    """256 independent instances (n, m log-uniform in [500, 4000] x [300, 3000],
+    p uniform in 5..20, 20 dB, l = p + 10, q = 2, 100 outer iterations): batched
+    RSI + batched compressed solve with the graph-captured outer loop, against
+    the same instances solved one after another on the single-instance path."""
+    dev = torch.device("cuda:0")
+    count, nu, q, T = 256, 10, 2, 100
+    shapes = synth.batched_shapes(count, seed=args.seed)
+    log(args, f"generating {count} instances")
+    descs, host_inst = [], []
+    for k, (n, m, p) in enumerate(shapes):
+        inst = synth.instance(n, m, p, nu, seed=1000 * args.seed + k, snr_db=20.0)
+        ld = (m + 63) // 64 * 64
+        Xb = torch.zeros(n, ld, device=dev)
+        Xb[:, :m] = torch.from_numpy(inst.X).to(dev)
+        ell = p + nu
+        d = dict(p=p, nu=nu, X=Xb[:, :m], omega_L=torch.from_numpy(inst.omega_L).to(dev),
+                 omega_R=torch.from_numpy(inst.omega_R).to(dev),
+                 Q_L=torch.empty(n, ell, device=dev), Q_R=torch.empty(m, ell, device=dev),
+                 X_L=torch.empty(ell, m, device=dev), X_R=torch.empty(n, ell, device=dev),
+                 G=torch.empty(n, p, device=dev), F=torch.empty(p, m, device=dev),
+                 G0=torch.from_numpy(inst.G0).to(dev), F0=torch.from_numpy(inst.F0).to(dev))
+        descs.append(d)
+    b = cnmf.Batch(descs, q=q, outer_iters=T, inner_max=args.inner_max)
+
+    def reset():
+        for d in descs:
+            d["G"].copy_(d["G0"])
+            d["F"].copy_(d["F0"])
+
+    reset()
+    b.rsi()
+    tiles = b.tune(3)
+    log(args, f"tuned tiles (G, F) = {tiles}")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def step():
+        reset()
+        ev[0].record()
+        b.rsi()
+        ev[1].record()
+        b.solve(True)
+        ev[2].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    cnmf.check()
+    t_rsi, t_solve = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        t_rsi.append(ev[0].elapsed_time(ev[1]) / 1e3)
+        t_solve.append(ev[1].elapsed_time(ev[2]) / 1e3)
+    wall = time.perf_counter() - t0
+    cnmf.check()
+    rre = []
+    for d in descs:
+        rre.append(float(cnmf.rre(d["X"], d["G"][None], d["F"][None]).cpu().numpy()[0]))
+    # the same work on the single-instance path, one instance after another
+    log(args, "single-instance path, sequential")
+    reset()
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    for d in descs:
+        comp = cnmf.rsi(d["X"], d["omega_L"], d["omega_R"], d["p"], nu, q,
+                        out=(d["Q_L"], d["Q_R"], d["X_L"], d["X_R"]))
+        cnmf.solve(d["G"], d["F"], compressed=comp, p=d["p"], nu=nu, outer_iters=T,
+                   inner_max=args.inner_max)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - s0
+    cnmf.check()
+    per = min(t_rsi[i] + t_solve[i] for i in range(len(t_rsi)))
+    rsi_s = min(t_rsi)
+    sweep_bytes = sum(2 * (2 * q + 1) * 4.0 * n * m for n, m, _ in shapes)
+    out = {
+        "metric": "batched compressed NeNMF: s for 256 uneven instances (RSI q=2 + 100 outer)",
+        "value": round(per, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256 instances, n log-U[500,4000], m log-U[300,3000], p U{5..20}, "
+                               "20 dB, l = p + 10, q = 2, 100 outer iterations, global bound 1e-3",
+                   "tiles": list(tiles), "elements": int(sum(n * m for n, m, _ in shapes))},
+        "rsi_s": round(rsi_s, 6), "solve_s": round(min(t_solve), 6),
+        "rsi_sweep_gbs": round(sweep_bytes / rsi_s / 1e9, 1),
+        "sequential_single_path_s": round(seq_s, 4),
+        "speedup_vs_sequential": round(seq_s / per, 2),
+        "rre_median": float(np.median(rre)), "rre_max": float(np.max(rre)),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -159,6 +256,8 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.form == "batched":
+        return bench_batched(args, torch, cnmf, synth)
     dev = torch.device("cuda:0")
     n, m, p, nu, q, T = args.n, args.m, args.p, args.nu, args.q, args.outer
     ell = p + nu

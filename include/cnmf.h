@@ -270,6 +270,30 @@ int cnmf_batch_tune(cnmf_batch* b, int32_t tune_iters, int32_t* tiles_out);
  * the whole loop in a HIP graph on first use and replays it afterwards. */
 int cnmf_batch_solve(cnmf_batch* b, int32_t use_graph);
 
+/* ---- differentiation form -------------------------------------------
+ * Reverse mode of compressed NeNMF (Algorithms 1 and 2, Sec. 2 inner loop)
+ * unrolled over T = prm->outer_iters outer iterations with exactly
+ * K = prm->inner_max (1..8) inner steps per subproblem.
+ * cnmf_adj_forward: randomized subspace iteration (prm->q, tau2) keeping
+ *   every panel, then the outer loop from (G0, F0), keeping (G, F) every
+ *   ckpt outer iterations; writes G_T, F_T and returns the tape.  X,
+ *   omega_L and omega_R must stay valid until the tape is destroyed.
+ * cnmf_adj_backward: given dL/dG_T (n x p) and dL/dF_T (p x m), writes
+ *   dL/dX (n x m, row pitch lddx) and, if non-NULL, dL/dG0, dL/dF0.  Each
+ *   checkpoint segment is recomputed; the subproblems are reversed through
+ *   their projections and momentum, L = lambda_max(W) through its top
+ *   eigenvector, the bases through the thin-QR adjoint (no basis column may
+ *   have been replaced by the rank rule).  The tape can be reused. */
+typedef struct cnmf_tape cnmf_tape;
+int cnmf_adj_forward(cnmf_ctx* ctx, int64_t n, int64_t m, const float* X, int64_t ldx,
+                     const cnmf_params* prm, int32_t ckpt, const float* omega_L,
+                     const float* omega_R, const float* G0, const float* F0,
+                     float* G_out, float* F_out, cnmf_tape** tape);
+int cnmf_adj_backward(cnmf_tape* tape, const float* dG, const float* dF, float* dX,
+                      int64_t lddx, float* dG0, float* dF0);
+int cnmf_tape_bytes(const cnmf_tape* tape, uint64_t* bytes /* host */);
+int cnmf_tape_destroy(cnmf_tape* tape);
+
 #ifdef __cplusplus
 }
 #endif

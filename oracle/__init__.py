@@ -10,3 +10,4 @@ from .nenmf import (  # noqa: F401
     g_data_compressed, f_data_compressed, nenmf, rre, svd_floor,
     bf16_bits, bf16_value, bf16_round,
 )
+from . import adjoint  # noqa: F401,E402

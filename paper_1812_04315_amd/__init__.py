@@ -33,7 +33,8 @@ EXPORTED = [
     "cnmf_sweep_right_bf16", "cnmf_sweep_left_bf16",
     "cnmf_orth", "cnmf_lipschitz", "cnmf_nnls",
     "cnmf_batch_create", "cnmf_batch_destroy", "cnmf_batch_rsi", "cnmf_batch_tune",
-    "cnmf_batch_solve",
+    "cnmf_batch_solve", "cnmf_adj_forward", "cnmf_adj_backward", "cnmf_tape_bytes",
+    "cnmf_tape_destroy",
 ]
 
 
@@ -111,6 +112,11 @@ def lib() -> ctypes.CDLL:
             "cnmf_batch_rsi": (ctypes.c_int, [P]),
             "cnmf_batch_tune": (ctypes.c_int, [P, I32, ctypes.POINTER(I32)]),
             "cnmf_batch_solve": (ctypes.c_int, [P, I32]),
+            "cnmf_adj_forward": (ctypes.c_int, [P, I64, I64, P, I64, ctypes.POINTER(Params), I32,
+                                                P, P, P, P, P, P, ctypes.POINTER(P)]),
+            "cnmf_adj_backward": (ctypes.c_int, [P, P, P, P, I64, P, P]),
+            "cnmf_tape_bytes": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_uint64)]),
+            "cnmf_tape_destroy": (ctypes.c_int, [P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -526,3 +532,101 @@ class Batch:
             self.close()
         except Exception:  # noqa: BLE001
             pass
+
+
+# ---------------------------------------------------------------------------
+# Differentiation form
+# ---------------------------------------------------------------------------
+class Tape:
+    """Forward state of an unrolled compressed-NeNMF run (library-owned)."""
+
+    def __init__(self, h, keep, shapes):
+        self.h = h
+        self._keep = keep          # X, omega_L, omega_R must outlive the tape
+        self.n, self.m, self.p = shapes
+
+    @property
+    def bytes(self) -> int:
+        v = ctypes.c_uint64()
+        _call("cnmf_tape_bytes", self.h, ctypes.byref(v))
+        return int(v.value)
+
+    def backward(self, dG, dF, want_factors: bool = True):
+        """dL/dX (n x m) and, optionally, dL/dG0, dL/dF0 from dL/dG_T, dL/dF_T."""
+        torch = _torch()
+        dG = dG.detach().float().contiguous()
+        dF = dF.detach().float().contiguous()
+        dX = torch.empty(self.n, self.m, device=dG.device)
+        dG0 = torch.empty_like(dG) if want_factors else None
+        dF0 = torch.empty_like(dF) if want_factors else None
+        _call("cnmf_adj_backward", self.h, _ptr(dG), _ptr(dF), _ptr(dX), self.m,
+              _ptr(dG0) if dG0 is not None else None, _ptr(dF0) if dF0 is not None else None)
+        return dX, dG0, dF0
+
+    def close(self):
+        if self.h:
+            lib().cnmf_tape_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+def adj_forward(X, omega_L, omega_R, G0, F0, *, p: int, nu: int = 10, q: int = 2,
+                outer_iters: int = 50, inner_steps: int = 5, ckpt: int = 10):
+    """Compressed NeNMF with exactly ``inner_steps`` inner steps, keeping the
+    tape for the reverse pass.  Returns (G_T, F_T, Tape)."""
+    torch = _torch()
+    _need(X, torch.float32, "X", ld_ok=True)
+    n, m = X.shape
+    ell = p + nu
+    _need(omega_L, torch.float32, "omega_L", (m, ell))
+    _need(omega_R, torch.float32, "omega_R", (ell, n))
+    _need(G0, torch.float32, "G0", (n, p))
+    _need(F0, torch.float32, "F0", (p, m))
+    G = torch.empty_like(G0)
+    F = torch.empty_like(F0)
+    prm = params(p, nu, q, outer_iters, inner_steps, stop_rule=STOP_SUBPROBLEM)
+    h = ctypes.c_void_p()
+    _call("cnmf_adj_forward", context().h, n, m, _ptr(X), _ld(X), ctypes.byref(prm), ckpt,
+          _ptr(omega_L), _ptr(omega_R), _ptr(G0), _ptr(F0), _ptr(G), _ptr(F), ctypes.byref(h))
+    return G, F, Tape(h, (X, omega_L, omega_R), (n, m, p))
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class CompressedNeNMF(torch.autograd.Function):
+        """(X, G0, F0) -> (G_T, F_T) of unrolled compressed NeNMF; backward by
+        the library's hand-written adjoint."""
+
+        @staticmethod
+        def forward(ctx, X, G0, F0, omega_L, omega_R, p, nu, q, outer_iters, inner_steps, ckpt):
+            Xc = X.detach().contiguous()
+            G, F, tape = adj_forward(Xc, omega_L.detach().contiguous(),
+                                     omega_R.detach().contiguous(), G0.detach().contiguous(),
+                                     F0.detach().contiguous(), p=p, nu=nu, q=q,
+                                     outer_iters=outer_iters, inner_steps=inner_steps, ckpt=ckpt)
+            ctx.tape = tape
+            return G, F
+
+        @staticmethod
+        def backward(ctx, gG, gF):
+            torch_ = _torch()
+            gG = torch_.zeros_like(ctx.tape._keep[0][:, :ctx.tape.p]) if gG is None else gG
+            gF = torch_.zeros(ctx.tape.p, ctx.tape.m, device=gG.device) if gF is None else gF
+            dX, dG0, dF0 = ctx.tape.backward(gG, gF)
+            return dX, dG0, dF0, None, None, None, None, None, None, None, None
+
+    return CompressedNeNMF
+
+
+def compressed_nenmf(X, G0, F0, omega_L, omega_R, *, p: int, nu: int = 10, q: int = 2,
+                     outer_iters: int = 50, inner_steps: int = 5, ckpt: int = 10):
+    """Differentiable compressed NeNMF: returns (G_T, F_T); gradients with
+    respect to X, G0 and F0 come from the hand-written adjoint."""
+    return _autograd_function().apply(X, G0, F0, omega_L, omega_R, p, nu, q, outer_iters,
+                                      inner_steps, ckpt)

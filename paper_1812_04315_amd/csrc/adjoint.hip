@@ -1,0 +1,900 @@
+// Differentiation form: reverse mode of compressed NeNMF (Sec. 3,
+// Algorithms 1 and 2) unrolled over T outer iterations with exactly K inner
+// Nesterov steps each (Sec. 2), giving dL/dX for a loss L(G_T, F_T).
+//
+// Forward: randomized subspace iteration keeping every sketch panel and its
+// basis (the tape), then the outer loop on the single-instance solver,
+// keeping (G, F) every `ckpt` outer iterations.  Backward: each segment of
+// `ckpt` iterations is recomputed from its checkpoint; every subproblem is
+// reversed through its K projected steps (masks 1[V > 0], the momentum
+// weights, the step 1/L with dL = v^T dW v for the top eigenvector v), its
+// small products, then the bases through the thin-QR adjoint and the X
+// products.  X enters only through products X A and X^T B, so
+// dL/dX = sum_j U_j V_j^T over 2(2q+1) rank-l pairs, formed by one final
+// U V^T product.
+#include <cmath>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxK = 8;   // inner steps per subproblem the reverse supports
+
+// ---------------------------------------------------------------------------
+// Small dense products C = alpha op(A) op(B) + beta C (row-major), for the
+// p x p, p x l, l x l, n x l, l x m shapes of the reverse pass.  Short
+// reductions: one thread per output; long ones: one wavefront per output.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float opA(const float* A, int64_t lda, int ta, int64_t i, int64_t k) {
+    return ta ? A[k * lda + i] : A[i * lda + k];
+}
+__device__ __forceinline__ float opB(const float* B, int64_t ldb, int tb, int64_t k, int64_t j) {
+    return tb ? B[j * ldb + k] : B[k * ldb + j];
+}
+
+__global__ __launch_bounds__(kThreads) void k_gemm_short(int64_t M, int64_t N, int64_t K,
+                                                        float alpha, const float* A, int64_t lda,
+                                                        int ta, const float* B, int64_t ldb,
+                                                        int tb, float beta, float* C,
+                                                        int64_t ldc) {
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= M * N) return;
+    const int64_t i = e / N, j = e - i * N;
+    float s = 0.f;
+    for (int64_t k = 0; k < K; ++k) s = fmaf(opA(A, lda, ta, i, k), opB(B, ldb, tb, k, j), s);
+    const float old = beta != 0.f ? C[i * ldc + j] : 0.f;
+    C[i * ldc + j] = alpha * s + beta * old;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gemm_long(int64_t M, int64_t N, int64_t K,
+                                                       float alpha, const float* A, int64_t lda,
+                                                       int ta, const float* B, int64_t ldb,
+                                                       int tb, float beta, float* C,
+                                                       int64_t ldc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= M * N) return;   // uniform per wave
+    const int64_t i = e / N, j = e - i * N;
+    float s = 0.f;
+    for (int64_t k = lane; k < K; k += 64) s = fmaf(opA(A, lda, ta, i, k), opB(B, ldb, tb, k, j), s);
+    s = wave_sum(s);
+    if (lane == 0) {
+        const float old = beta != 0.f ? C[i * ldc + j] : 0.f;
+        C[i * ldc + j] = alpha * s + beta * old;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, float alpha, const float* x, float* y) {
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e < n) y[e] += alpha * x[e];
+}
+
+// dst (rows x cols, ldd) = src (rows x cols, lds)
+__global__ __launch_bounds__(kThreads) void k_copy2d(int64_t rows, int64_t cols, const float* src,
+                                                    int64_t lds, float* dst, int64_t ldd) {
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= rows * cols) return;
+    const int64_t r = e / cols, c = e - r * cols;
+    dst[r * ldd + c] = src[r * lds + c];
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_f(int64_t n, float v, float* y) {
+    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (e < n) y[e] = v;
+}
+
+// C = tril(M) + tril(M, -1)^T  (l x l)
+__global__ __launch_bounds__(kThreads) void k_copyltu(int l, const float* M, float* C) {
+    for (int e = threadIdx.x; e < l * l; e += kThreads) {
+        const int i = e / l, j = e % l;
+        C[e] = i >= j ? M[i * l + j] : M[j * l + i];
+    }
+}
+
+// Ri = R^-1 for the upper triangle of R (l x l), FP64, lane c owns column c.
+__global__ __launch_bounds__(64) void k_tri_inv(int l, const float* R, float* Ri) {
+    __shared__ double sR[32][33];
+    for (int e = threadIdx.x; e < l * l; e += 64) sR[e / l][e % l] = (double)R[e];
+    __syncthreads();
+    const int c = threadIdx.x;
+    if (c < l) {
+        double x[32];
+        for (int i = 0; i < 32; ++i) x[i] = 0.0;
+        for (int i = l - 1; i >= 0; --i) {
+            if (i > c) continue;
+            double s = i == c ? 1.0 : 0.0;
+            for (int t = i + 1; t <= c; ++t) s -= sR[i][t] * x[t];
+            x[i] = s / sR[i][i];
+        }
+        for (int i = 0; i < l; ++i) Ri[i * l + c] = (float)x[i];
+    }
+}
+
+// Unit eigenvector of the symmetric p x p W for its largest eigenvalue L, by
+// inverse iteration with the shift L (1 + 1e-9) in FP64 (Gaussian
+// elimination with partial pivoting, one wavefront, lane = row).
+__global__ __launch_bounds__(64) void k_eigvec(int p, const float* W, const double* Lp, float* v) {
+    __shared__ double A[32][33];
+    __shared__ double x[32];
+    __shared__ int piv;
+    const int lane = threadIdx.x;
+    const double L = *Lp;
+    const double sigma = L * (1.0 + 1e-9) + 1e-300;
+    if (lane < p) x[lane] = 1.0 / sqrt((double)p);
+    __syncthreads();
+    for (int it = 0; it < 3; ++it) {
+        for (int e = lane; e < p * p; e += 64) {
+            const int i = e / p, j = e % p;
+            A[i][j] = 0.5 * ((double)W[i * p + j] + (double)W[j * p + i]) - (i == j ? sigma : 0.0);
+        }
+        __syncthreads();
+        // forward elimination with partial pivoting on [A | x]
+        for (int k = 0; k < p; ++k) {
+            if (lane == 0) {
+                int best = k;
+                for (int i = k + 1; i < p; ++i)
+                    if (fabs(A[i][k]) > fabs(A[best][k])) best = i;
+                piv = best;
+            }
+            __syncthreads();
+            const int pr = piv;
+            if (pr != k) {
+                if (lane <= p) {
+                    const int j = lane;
+                    if (j < p) {
+                        const double t = A[k][j];
+                        A[k][j] = A[pr][j];
+                        A[pr][j] = t;
+                    } else {
+                        const double t = x[k];
+                        x[k] = x[pr];
+                        x[pr] = t;
+                    }
+                }
+            }
+            __syncthreads();
+            double akk = A[k][k];
+            if (akk == 0.0) akk = 1e-300;
+            if (lane > k && lane < p) {
+                const double f = A[lane][k] / akk;
+                for (int j = k; j < p; ++j) A[lane][j] -= f * A[k][j];
+                x[lane] -= f * x[k];
+            }
+            __syncthreads();
+        }
+        // back substitution (lane 0), then normalise
+        if (lane == 0) {
+            for (int i = p - 1; i >= 0; --i) {
+                double s = x[i];
+                for (int j = i + 1; j < p; ++j) s -= A[i][j] * x[j];
+                double aii = A[i][i];
+                if (aii == 0.0) aii = 1e-300;
+                x[i] = s / aii;
+            }
+            double nrm = 0.0;
+            for (int i = 0; i < p; ++i) nrm += x[i] * x[i];
+            nrm = sqrt(nrm);
+            // fix the sign: largest component positive
+            int big = 0;
+            for (int i = 1; i < p; ++i)
+                if (fabs(x[i]) > fabs(x[big])) big = i;
+            const double sg = x[big] < 0.0 ? -1.0 : 1.0;
+            for (int i = 0; i < p; ++i) x[i] = sg * x[i] / (nrm > 0.0 ? nrm : 1.0);
+        }
+        __syncthreads();
+    }
+    if (lane < p) v[lane] = (float)x[lane];
+}
+
+// ---------------------------------------------------------------------------
+// Reverse of one Nesterov subproblem over `rows` independent rows (Sec. 2):
+//   Y_k = Z_{k-1} + b_k (Z_{k-1} - Z_{k-2})   (Z_{-1} = Z_0, b_1 = b_2 = 0)
+//   V_k = Y_k - (Y_k W - b) / L,   Z_k = max(0, V_k),   k = 1..K.
+// Given Zbar = dL/dZ_K: Z0bar, Bbar (per row), Ys / Vbars (for
+// Wbar = -(1/L) sum_k Y_k^T Vbar_k) and per-block partials of
+// Lbar = sum_k <Vbar_k, Y_k - V_k> / L.
+// ---------------------------------------------------------------------------
+struct AdjNnls {
+    int64_t rows;
+    int p, K;
+    const float* Z0;
+    int64_t z_rs, z_cs;
+    const float* W;
+    const float* B;
+    int64_t b_rs, b_cs;
+    const double* L;
+    const float* Zbar;
+    float* Z0bar;            // same strides as Z0
+    float* Bbar;             // same strides as B
+    float* Zs;               // [K + 1][rows][32]
+    float* Ys;               // [K][rows][p]
+    float* Vb;               // [K][rows][p]
+    double* Lpart;           // [gridDim.x]
+    float beta[kMaxK + 1];   // beta[k] = b_k, k = 1..K
+};
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_nnls_adj(AdjNnls a) {
+    __shared__ float sW[32][33];
+    __shared__ double sred[4];
+    const int p = a.p;
+    for (int e = threadIdx.x; e < p * p; e += kThreads) sW[e / p][e % p] = a.W[e];
+    __syncthreads();
+    const double Ld = *a.L;
+    const float invL = (float)(1.0 / Ld);
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    double lbar = 0.0;
+    if (r < a.rows) {
+        float b[P], zc[P], zp[P];
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            b[c] = c < p ? a.B[r * a.b_rs + c * a.b_cs] : 0.f;
+            zc[c] = c < p ? a.Z0[r * a.z_rs + c * a.z_cs] : 0.f;
+            zp[c] = zc[c];
+        }
+        auto zs = [&](int k) { return a.Zs + ((int64_t)k * a.rows + r) * 32; };
+#pragma unroll
+        for (int c = 0; c < P; ++c) zs(0)[c] = zc[c];
+        // forward recompute, keeping Z_0 .. Z_K
+        for (int k = 1; k <= a.K; ++k) {
+            const float bk = a.beta[k];
+            float y[P], zn[P];
+#pragma unroll
+            for (int c = 0; c < P; ++c) y[c] = fmaf(bk, zc[c] - zp[c], zc[c]);
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                float g = -b[c];
+#pragma unroll
+                for (int d = 0; d < P; ++d) g = fmaf(y[d], d < p && c < p ? sW[d][c] : 0.f, g);
+                const float v = fmaf(-g, invL, y[c]);
+                zn[c] = (v > 0.f || v != v) ? v : 0.f;
+            }
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                zp[c] = zc[c];
+                zc[c] = zn[c];
+                zs(k)[c] = zn[c];
+            }
+        }
+        // reverse: za = dL/dZ_k (complete), zb = dL/dZ_{k-1}, zq = dL/dZ_{k-2}
+        float za[P], zb[P], zq[P], bb[P];
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            za[c] = c < p ? a.Zbar[r * a.z_rs + c * a.z_cs] : 0.f;
+            zb[c] = 0.f;
+            zq[c] = 0.f;
+            bb[c] = 0.f;
+        }
+        for (int k = a.K; k >= 1; --k) {
+            const float bk = a.beta[k];
+            const float* z1 = zs(k - 1);
+            const float* z2 = zs(k >= 2 ? k - 2 : 0);
+            float y[P], vb[P];
+#pragma unroll
+            for (int c = 0; c < P; ++c) y[c] = fmaf(bk, z1[c] - z2[c], z1[c]);
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                float g = -b[c];
+#pragma unroll
+                for (int d = 0; d < P; ++d) g = fmaf(y[d], d < p && c < p ? sW[d][c] : 0.f, g);
+                const float v = fmaf(-g, invL, y[c]);
+                vb[c] = (v > 0.f) ? za[c] : 0.f;
+                lbar += (double)vb[c] * (double)(y[c] - v);
+            }
+            float* ys = a.Ys + ((int64_t)(k - 1) * a.rows + r) * p;
+            float* vs = a.Vb + ((int64_t)(k - 1) * a.rows + r) * p;
+            for (int c = 0; c < p; ++c) {
+                ys[c] = y[c];
+                vs[c] = vb[c];
+            }
+            // ybar = vbar (I - W / L)^T, with V = Y (I - W/L) + b / L
+            float yb[P];
+#pragma unroll
+            for (int d = 0; d < P; ++d) {
+                float s = 0.f;
+#pragma unroll
+                for (int c = 0; c < P; ++c) s = fmaf(vb[c], d < p && c < p ? sW[d][c] : 0.f, s);
+                yb[d] = fmaf(-s, invL, vb[d]);
+            }
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                bb[c] = fmaf(vb[c], invL, bb[c]);
+                if (k >= 2) {
+                    zb[c] = fmaf(1.f + bk, yb[c], zb[c]);
+                    zq[c] = fmaf(-bk, yb[c], zq[c]);
+                } else {
+                    zb[c] += yb[c];   // Z_{-1} is Z_0
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                za[c] = zb[c];
+                zb[c] = zq[c];
+                zq[c] = 0.f;
+            }
+        }
+        for (int c = 0; c < p; ++c) {
+            a.Z0bar[r * a.z_rs + c * a.z_cs] = za[c];
+            a.Bbar[r * a.b_rs + c * a.b_cs] = bb[c];
+        }
+        lbar /= Ld;
+    }
+    lbar = wave_sum(lbar);
+    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = lbar;
+    __syncthreads();
+    if (threadIdx.x == 0) a.Lpart[blockIdx.x] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
+}
+
+// Wbar[d][c] = -(1/L) sum_s Ys[s][d] Vb[s][c] + Lbar v_d v_c, Lbar = sum of
+// the partials; one wavefront per entry.
+__global__ __launch_bounds__(kThreads) void k_wbar(int p, int64_t S, const float* Ys,
+                                                  const float* Vb, const double* Lp,
+                                                  const double* Lpart, int nparts,
+                                                  const float* v, float* Wbar) {
+    const int lane = threadIdx.x & 63;
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= p * p) return;
+    const int d = e / p, c = e % p;
+    double s = 0.0;
+    for (int64_t k = lane; k < S; k += 64) s += (double)Ys[k * p + d] * (double)Vb[k * p + c];
+    s = wave_sum(s);
+    double lb = 0.0;
+    for (int k = lane; k < nparts; k += 64) lb += Lpart[k];
+    lb = wave_sum(lb);
+    if (lane == 0) Wbar[e] = (float)(-s / *Lp + lb * (double)v[d] * (double)v[c]);
+}
+
+// dX (n x m, ldd) = U V^T with U n x r, V m x r (row-major): 64 x 64 tiles,
+// 4 x 4 outputs per thread, reduction staged through LDS in chunks of 16.
+__global__ __launch_bounds__(kThreads) void k_gemm_nt(int64_t n, int64_t m, int r, const float* U,
+                                                     const float* V, float* dX, int64_t ldd) {
+    __shared__ float su[16][68], sv[16][68];
+    const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    float acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+    for (int k0 = 0; k0 < r; k0 += 16) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 16 * 64; e += kThreads) {
+            const int kk = e % 16, rr = e / 16;
+            const int64_t iu = i0 + rr, jv = j0 + rr;
+            const int k = k0 + kk;
+            su[kk][rr] = (iu < n && k < r) ? U[iu * r + k] : 0.f;
+            sv[kk][rr] = (jv < m && k < r) ? V[jv * r + k] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            float a4[4], b4[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) a4[a] = su[kk][ty * 4 + a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) b4[b] = sv[kk][tx * 4 + b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(a4[a], b4[b], acc[a][b]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t i = i0 + ty * 4 + a, j = j0 + tx * 4 + b;
+            if (i < n && j < m) dX[i * ldd + j] = acc[a][b];
+        }
+}
+
+unsigned nb(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct cnmf_tape {
+    cnmf_ctx* c = nullptr;
+    int64_t n = 0, m = 0, ldx = 0, ldt = 0;
+    int p = 0, l = 0, q = 0, T = 0, K = 0, ck = 0;
+    const float* X = nullptr;
+    const float* oL = nullptr;
+    const float* oR = nullptr;
+    char* mem = nullptr;
+    size_t bytes = 0;
+    // RSI tape (see rsi_forward)
+    float *oRt = nullptr, *oLT = nullptr;
+    std::vector<float*> A, QL, Cn, QtRt;        // n x l panels
+    std::vector<float*> Bm, QRt, Cm, QtL;       // m x l panels
+    std::vector<float*> QRtT, QtLT;             // transposes, l x ldt
+    float *QLo = nullptr, *QRo = nullptr, *XL = nullptr, *XR = nullptr;   // compressed data
+    // checkpoints and segment recompute
+    std::vector<float*> Gc, Fc;                 // (G, F) at t = 0, ck, 2 ck, ...
+    float *Gh = nullptr, *Fh = nullptr;         // ck x n x p, ck x p x m
+    int32_t* replay = nullptr;                  // T x 2, all K
+    float* part = nullptr;                      // sweep partials
+    // reverse work buffers
+    float *Gb = nullptr, *Fb = nullptr, *Gb2 = nullptr, *Fb2 = nullptr;
+    float *XRb = nullptr, *XLb = nullptr, *QLb = nullptr, *QRb = nullptr;
+    float *GL = nullptr, *FR = nullptr, *W = nullptr, *Bsub = nullptr, *Bb = nullptr, *Wb = nullptr;
+    float *GLb = nullptr, *FRb = nullptr, *v = nullptr;
+    double* L = nullptr;
+    float *Zs = nullptr, *Ys = nullptr, *Vb = nullptr;
+    double* Lpart = nullptr;
+    float *U = nullptr, *V = nullptr;           // n x r, m x r
+    float *Tn = nullptr, *Tm = nullptr, *Tn2 = nullptr, *Tm2 = nullptr;   // panel temporaries
+    float *Rl = nullptr, *Ril = nullptr, *Ml = nullptr, *Cl = nullptr;   // l x l
+    std::vector<float*> QLb_k, QRtb_k;          // adjoints of QL_k, QRt_k (k < q)
+};
+
+namespace {
+
+hipError_t gemm(const Dev& d, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
+                int64_t lda, bool ta, const float* B, int64_t ldb, bool tb, float beta, float* C,
+                int64_t ldc) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (K > 64)
+        hipLaunchKernelGGL(k_gemm_long, dim3(nb(M * N, 4)), dim3(kThreads), 0, d.stream, M, N, K,
+                           alpha, A, lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, beta, C, ldc);
+    else
+        hipLaunchKernelGGL(k_gemm_short, dim3(nb(M * N, kThreads)), dim3(kThreads), 0, d.stream, M,
+                           N, K, alpha, A, lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, beta, C, ldc);
+    return hipGetLastError();
+}
+
+hipError_t axpy(const Dev& d, int64_t n, float alpha, const float* x, float* y) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpy, dim3(nb(n, kThreads)), dim3(kThreads), 0, d.stream, n, alpha, x, y);
+    return hipGetLastError();
+}
+
+hipError_t fillf(const Dev& d, int64_t n, float v, float* y) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f, dim3(nb(n, kThreads)), dim3(kThreads), 0, d.stream, n, v, y);
+    return hipGetLastError();
+}
+
+hipError_t copy2d(const Dev& d, int64_t rows, int64_t cols, const float* src, int64_t lds,
+                  float* dst, int64_t ldd) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy2d, dim3(nb(rows * cols, kThreads)), dim3(kThreads), 0, d.stream,
+                       rows, cols, src, lds, dst, ldd);
+    return hipGetLastError();
+}
+
+#define HK(x)                                   \
+    do {                                        \
+        hipError_t e_ = (x);                    \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
+// Thin-QR adjoint of Q = qr(Y) (R unused downstream), N x l panels:
+//   M = -Qbar^T Q,  Ybar = (Qbar + Q copyltu(M)) R^-T,  R = Q^T Y.
+hipError_t orth_adj(cnmf_tape* t, const Dev& d, int64_t N, const float* Y, const float* Q,
+                    const float* Qb, float* Yb, float* tmp) {
+    const int l = t->l;
+    HK(gemm(d, l, l, N, 1.f, Q, l, true, Y, l, false, 0.f, t->Rl, l));
+    HK(gemm(d, l, l, N, -1.f, Qb, l, true, Q, l, false, 0.f, t->Ml, l));
+    hipLaunchKernelGGL(k_copyltu, dim3(1), dim3(kThreads), 0, d.stream, l, t->Ml, t->Cl);
+    HK(hipGetLastError());
+    hipLaunchKernelGGL(k_tri_inv, dim3(1), dim3(64), 0, d.stream, l, t->Rl, t->Ril);
+    HK(hipGetLastError());
+    HK(copy2d(d, N, l, Qb, l, tmp, l));
+    HK(gemm(d, N, l, l, 1.f, Q, l, false, t->Cl, l, false, 1.f, tmp, l));
+    return gemm(d, N, l, l, 1.f, tmp, l, false, t->Ril, l, true, 0.f, Yb, l);
+}
+
+// Forward randomized subspace iteration keeping every panel (Algorithm 2,
+// the same chain and kernels as the plain entry point).
+int rsi_forward(cnmf_tape* t) {
+    cnmf_ctx* c = t->c;
+    const Dev& d = c->dev;
+    const int64_t n = t->n, m = t->m;
+    const int l = t->l, q = t->q;
+    const double tau2 = 1e-9;
+    auto orth_n = [&](const float* Y, float* Q) -> hipError_t {
+        unsigned seq = 0;
+        HK(next_seq(c, &seq));
+        return orth(d, n, l, Y, t->oRt, false, tau2, Q, nullptr, 0, nullptr, c->oxch, seq, c->ctl);
+    };
+    auto orth_m = [&](const float* Y, float* Q, float* QT) -> hipError_t {
+        unsigned seq = 0;
+        HK(next_seq(c, &seq));
+        return orth(d, m, l, Y, t->oL, false, tau2, Q, QT, t->ldt, nullptr, c->oxch, seq, c->ctl);
+    };
+    auto right = [&](const float* AT, float* Y) {
+        return sweep_right(d, n, m, t->X, t->ldx, l, AT, t->ldt, true, Y, l, t->part);
+    };
+    auto left = [&](const float* B, float* Z) {
+        return sweep_left(d, n, m, t->X, t->ldx, l, B, l, Z, l, false, t->part);
+    };
+    CK(transpose(d, l, n, t->oR, n, t->oRt, l));
+    CK(transpose(d, m, l, t->oL, l, t->oLT, t->ldt));
+    CK(right(t->oLT, t->A[0]));
+    CK(orth_n(t->A[0], t->QL[0]));
+    CK(left(t->oRt, t->Bm[0]));
+    CK(orth_m(t->Bm[0], t->QRt[0], t->QRtT[0]));
+    for (int k = 1; k <= q; ++k) {
+        CK(left(t->QL[k - 1], t->Cm[k]));
+        CK(orth_m(t->Cm[k], t->QtL[k], t->QtLT[k]));
+        CK(right(t->QRtT[k - 1], t->Cn[k]));
+        CK(orth_n(t->Cn[k], t->QtRt[k]));
+        CK(right(t->QtLT[k], t->A[k]));
+        CK(left(t->QtRt[k], t->Bm[k]));
+        if (k < q) {
+            CK(orth_n(t->A[k], t->QL[k]));
+            CK(orth_m(t->Bm[k], t->QRt[k], t->QRtT[k]));
+        }
+    }
+    // compressed data: Q_L = Q~_R^(q)^T panel, Q_R = Q~_L^(q), X_R = A_q, X_L = B_q^T
+    t->QLo = t->QtRt[q];
+    t->QRo = t->QtL[q];
+    t->XR = t->A[q];
+    CK(transpose(d, m, l, t->Bm[q], l, t->XL, m));
+    return CNMF_OK;
+}
+
+// Outer iterations [t0, t0 + cnt) from (G, F) in place; with hist, every
+// iterate is kept (segment recompute).
+int solve_span(cnmf_tape* t, float* G, float* F, int t0, int cnt, bool hist) {
+    cnmf_params prm;
+    cnmf_params_default(&prm);
+    prm.p = t->p;
+    prm.nu = t->l - t->p;
+    prm.q = t->q;
+    prm.outer_iters = cnt;
+    prm.inner_max = t->K;
+    prm.stop_rule = CNMF_STOP_SUBPROBLEM;
+    cnmf_trace tr{};
+    if (hist) {
+        tr.G_hist = t->Gh;
+        tr.F_hist = t->Fh;
+    }
+    return cnmf_solve(t->c, CNMF_METHOD_COMPRESSED, t->n, t->m, nullptr, 0, t->QLo, t->QRo, t->XL,
+                      t->XR, &prm, G, F, hist ? &tr : nullptr, t->replay + 2 * t0);
+}
+
+// Reverse of one subproblem: Zbar (adjoint of its output) -> Z0bar, and the
+// adjoints of its W, B and L folded into Wb (p x p) and Bb (strided like B).
+int subproblem_adj(cnmf_tape* t, const Dev& d, int64_t rows, const float* Z0, int64_t z_rs,
+                   int64_t z_cs, const float* B, int64_t b_rs, int64_t b_cs, const float* Zbar,
+                   float* Z0bar) {
+    const int p = t->p;
+    CK(lipschitz(d, p, t->W, t->L, t->c->ctl));
+    hipLaunchKernelGGL(k_eigvec, dim3(1), dim3(64), 0, d.stream, p, t->W, t->L, t->v);
+    CK(hipGetLastError());
+    AdjNnls a{};
+    a.rows = rows;
+    a.p = p;
+    a.K = t->K;
+    a.Z0 = Z0;
+    a.z_rs = z_rs;
+    a.z_cs = z_cs;
+    a.W = t->W;
+    a.B = B;
+    a.b_rs = b_rs;
+    a.b_cs = b_cs;
+    a.L = t->L;
+    a.Zbar = Zbar;
+    a.Z0bar = Z0bar;
+    a.Bbar = t->Bb;
+    a.Zs = t->Zs;
+    a.Ys = t->Ys;
+    a.Vb = t->Vb;
+    a.Lpart = t->Lpart;
+    // momentum weights of the forward kernel: step k uses (alpha_{k-2} - 1) / alpha_{k-1}
+    double alpha = 1.0;
+    a.beta[0] = 0.f;
+    a.beta[1] = 0.f;
+    for (int k = 2; k <= t->K; ++k) {
+        const double an = 0.5 * (1.0 + std::sqrt(4.0 * alpha * alpha + 1.0));
+        a.beta[k] = (float)((alpha - 1.0) / an);
+        alpha = an;
+    }
+    const unsigned blocks = nb(rows, kThreads);
+    if (p <= 16) hipLaunchKernelGGL(k_nnls_adj<16>, dim3(blocks), dim3(kThreads), 0, d.stream, a);
+    else hipLaunchKernelGGL(k_nnls_adj<32>, dim3(blocks), dim3(kThreads), 0, d.stream, a);
+    CK(hipGetLastError());
+    hipLaunchKernelGGL(k_wbar, dim3(nb(p * p, 4)), dim3(kThreads), 0, d.stream, p,
+                       (int64_t)t->K * rows, t->Ys, t->Vb, t->L, t->Lpart, (int)blocks, t->v,
+                       t->Wb);
+    CK(hipGetLastError());
+    return CNMF_OK;
+}
+
+// Reverse of outer iteration t: (Gb, Fb) hold dL/dG_t, dL/dF_t on entry and
+// dL/dG_{t-1}, dL/dF_{t-1} on exit; the compressed-data adjoints accumulate.
+int outer_adj(cnmf_tape* t, const float* Gprev, const float* Fprev, const float* Gcur) {
+    const Dev& d = t->c->dev;
+    const int64_t n = t->n, m = t->m;
+    const int p = t->p, l = t->l;
+    // ---- F update: F_t = NNLS(F_{t-1}; W = G_L^T G_L, B = G_L^T X_L), G_L = Q_L^T G_t
+    CK(gemm(d, l, p, n, 1.f, t->QLo, l, true, Gcur, p, false, 0.f, t->GL, p));
+    CK(gemm(d, p, p, l, 1.f, t->GL, p, true, t->GL, p, false, 0.f, t->W, p));
+    CK(gemm(d, p, m, l, 1.f, t->GL, p, true, t->XL, m, false, 0.f, t->Bsub, m));
+    int rc = subproblem_adj(t, d, m, Fprev, 1, m, t->Bsub, 1, m, t->Fb, t->Fb2);
+    if (rc) return rc;
+    // G_L bar = G_L (Wb + Wb^T) + X_L Bb^T ; X_L bar += G_L Bb
+    CK(gemm(d, l, p, p, 1.f, t->GL, p, false, t->Wb, p, false, 0.f, t->GLb, p));
+    CK(gemm(d, l, p, p, 1.f, t->GL, p, false, t->Wb, p, true, 1.f, t->GLb, p));
+    CK(gemm(d, l, p, m, 1.f, t->XL, m, false, t->Bb, m, true, 1.f, t->GLb, p));
+    CK(gemm(d, l, m, p, 1.f, t->GL, p, false, t->Bb, m, false, 1.f, t->XLb, m));
+    // G_t bar += Q_L G_L bar ; Q_L bar += G_t G_L bar^T
+    CK(gemm(d, n, p, l, 1.f, t->QLo, l, false, t->GLb, p, false, 1.f, t->Gb, p));
+    CK(gemm(d, n, l, p, 1.f, Gcur, p, false, t->GLb, p, true, 1.f, t->QLb, l));
+    // ---- G update: G_t = NNLS(G_{t-1}; W = F_R F_R^T, B = X_R F_R^T), F_R = F_{t-1} Q_R
+    CK(gemm(d, p, l, m, 1.f, Fprev, m, false, t->QRo, l, false, 0.f, t->FR, l));
+    CK(gemm(d, p, p, l, 1.f, t->FR, l, false, t->FR, l, true, 0.f, t->W, p));
+    CK(gemm(d, n, p, l, 1.f, t->XR, l, false, t->FR, l, true, 0.f, t->Bsub, p));
+    rc = subproblem_adj(t, d, n, Gprev, p, 1, t->Bsub, p, 1, t->Gb, t->Gb2);
+    if (rc) return rc;
+    // F_R bar = (Wb + Wb^T) F_R + Bb^T X_R ; X_R bar += Bb F_R
+    CK(gemm(d, p, l, p, 1.f, t->Wb, p, false, t->FR, l, false, 0.f, t->FRb, l));
+    CK(gemm(d, p, l, p, 1.f, t->Wb, p, true, t->FR, l, false, 1.f, t->FRb, l));
+    CK(gemm(d, p, l, n, 1.f, t->Bb, p, true, t->XR, l, false, 1.f, t->FRb, l));
+    CK(gemm(d, n, l, p, 1.f, t->Bb, p, false, t->FR, l, false, 1.f, t->XRb, l));
+    // F_{t-1} bar += F_R bar Q_R^T ; Q_R bar += F_{t-1}^T F_R bar
+    CK(gemm(d, p, m, l, 1.f, t->FRb, l, false, t->QRo, l, true, 1.f, t->Fb2, m));
+    CK(gemm(d, m, l, p, 1.f, Fprev, m, true, t->FRb, l, false, 1.f, t->QRb, l));
+    std::swap(t->Gb, t->Gb2);
+    std::swap(t->Fb, t->Fb2);
+    return CNMF_OK;
+}
+
+// Reverse of Algorithm 2 from the compressed-data adjoints; the rank-l pairs
+// of dL/dX go to columns of U (n x r) and V (m x r).
+int rsi_adj(cnmf_tape* t) {
+    const Dev& d = t->c->dev;
+    const int64_t n = t->n, m = t->m;
+    const int l = t->l, q = t->q;
+    const int r = 2 * (2 * q + 1) * l;
+    int col = 0;
+    auto pair = [&](const float* Up, const float* Vp) -> hipError_t {
+        HK(copy2d(d, n, l, Up, l, t->U + col, r));
+        HK(copy2d(d, m, l, Vp, l, t->V + col, r));
+        col += l;
+        return hipSuccess;
+    };
+    auto right = [&](const float* A, float* Y) {   // Y = X A, A m x l
+        return sweep_right(d, n, m, t->X, t->ldx, l, A, l, false, Y, l, t->part);
+    };
+    auto left = [&](const float* B, float* Z) {    // Z = X^T B, B n x l
+        return sweep_left(d, n, m, t->X, t->ldx, l, B, l, Z, l, false, t->part);
+    };
+    // adjoints of X_R (= A_q) and X_L^T (= B_q)
+    float* Ab = t->XRb;
+    CK(transpose(d, l, m, t->XLb, m, t->Tm2, l));   // Bb_q (m x l)
+    float* Bb = t->Tm2;
+    float* QtRtb = t->QLb;   // dL/dQ~_R^(q) panel = dL/dQ_L
+    float* QtLb = t->QRb;    // dL/dQ~_L^(q) = dL/dQ_R
+    for (int k = q; k >= 1; --k) {
+        if (k < q) {
+            // A_k -> QL_k, B_k -> QRt_k
+            CK(orth_adj(t, d, n, t->A[k], t->QL[k], t->QLb_k[k], t->Tn2, t->Tn));
+            Ab = t->Tn2;
+            CK(orth_adj(t, d, m, t->Bm[k], t->QRt[k], t->QRtb_k[k], t->Tm2, t->Tm));
+            Bb = t->Tm2;
+            // the bases of this half-step start from zero
+            CK(fillf(d, n * l, 0.f, t->QLb));
+            CK(fillf(d, m * l, 0.f, t->QRb));
+            QtRtb = t->QLb;
+            QtLb = t->QRb;
+        }
+        // B_k = X^T QtRt_k: pair (QtRt_k, Bb_k), QtRt_k bar += X Bb_k
+        CK(pair(t->QtRt[k], Bb));
+        CK(right(Bb, t->Tn));
+        CK(axpy(d, n * l, 1.f, t->Tn, QtRtb));
+        // A_k = X QtL_k: pair (Ab_k, QtL_k), QtL_k bar += X^T Ab_k
+        CK(pair(Ab, t->QtL[k]));
+        CK(left(Ab, t->Tm));
+        CK(axpy(d, m * l, 1.f, t->Tm, QtLb));
+        // QtRt_k = orth(Cn_k), Cn_k = X QRt_{k-1}
+        CK(orth_adj(t, d, n, t->Cn[k], t->QtRt[k], QtRtb, t->Tn2, t->Tn));
+        CK(pair(t->Tn2, t->QRt[k - 1]));
+        CK(left(t->Tn2, t->QRtb_k[k - 1]));
+        // QtL_k = orth(Cm_k), Cm_k = X^T QL_{k-1}
+        CK(orth_adj(t, d, m, t->Cm[k], t->QtL[k], QtLb, t->Tm2, t->Tm));
+        CK(pair(t->QL[k - 1], t->Tm2));
+        CK(right(t->Tm2, t->QLb_k[k - 1]));
+    }
+    // step 0: QRt_0 = orth(B_0), B_0 = X^T Omega_R^T ; QL_0 = orth(A_0), A_0 = X Omega_L
+    CK(orth_adj(t, d, m, t->Bm[0], t->QRt[0], t->QRtb_k[0], t->Tm2, t->Tm));
+    CK(pair(t->oRt, t->Tm2));
+    CK(orth_adj(t, d, n, t->A[0], t->QL[0], t->QLb_k[0], t->Tn2, t->Tn));
+    CK(pair(t->Tn2, t->oL));
+    return col == r ? CNMF_OK : CNMF_EINVAL;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cnmf_adj_forward(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t ldx,
+                     const cnmf_params* prm, int32_t ckpt, const float* omega_L,
+                     const float* omega_R, const float* G0, const float* F0, float* G_out,
+                     float* F_out, cnmf_tape** tape_out) {
+    if (!c || !tape_out || !prm) return CNMF_EINVAL;
+    *tape_out = nullptr;
+    if (check_params(prm, n, m, true)) return CNMF_EINVAL;
+    if (prm->p > 32 || prm->inner_max < 1 || prm->inner_max > kMaxK) return CNMF_EINVAL;
+    if (ckpt < 1 || prm->outer_iters < 1) return CNMF_EINVAL;
+    if (bad_ptr(X) || ldx < m || bad_ptr(omega_L) || bad_ptr(omega_R) || bad_ptr(G0) ||
+        bad_ptr(F0) || bad_ptr(G_out) || bad_ptr(F_out))
+        return CNMF_EINVAL;
+    if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
+    cnmf_tape* t = new (std::nothrow) cnmf_tape;
+    if (!t) return CNMF_ENOMEM;
+    t->c = c;
+    t->n = n;
+    t->m = m;
+    t->X = X;
+    t->ldx = ldx;
+    t->oL = omega_L;
+    t->oR = omega_R;
+    t->p = prm->p;
+    t->l = prm->p + prm->nu;
+    t->q = prm->q;
+    t->T = prm->outer_iters;
+    t->K = prm->inner_max;
+    t->ck = ckpt;
+    t->ldt = (m + 3) / 4 * 4;
+    const int l = t->l, q = t->q, p = t->p, T = t->T;
+    const int r = 2 * (2 * q + 1) * l;
+    const int nck = (T + ckpt - 1) / ckpt + 1;
+    Arena ar;
+    std::vector<size_t> o;
+    auto take = [&](size_t floats) { o.push_back(ar.take<float>(floats)); };
+    const size_t NL = (size_t)n * l, ML = (size_t)m * l, LT = (size_t)l * t->ldt;
+    take(NL);            // 0 oRt
+    take(LT);            // 1 oLT
+    for (int k = 0; k <= q; ++k) { take(NL); take(NL); take(NL); take(NL); }   // A, QL, Cn, QtRt
+    for (int k = 0; k <= q; ++k) { take(ML); take(ML); take(ML); take(ML); }   // Bm, QRt, Cm, QtL
+    for (int k = 0; k <= q; ++k) { take(LT); take(LT); }                       // QRtT, QtLT
+    take((size_t)l * m);                                                       // XL
+    for (int k = 0; k < nck; ++k) { take((size_t)n * p); take((size_t)p * m); }   // checkpoints
+    take((size_t)ckpt * n * p);
+    take((size_t)ckpt * p * m);
+    const size_t o_rep = ar.take<int32_t>((size_t)2 * T);
+    const size_t pf = std::max(sweep_right_partial_floats(c->dev, n, m),
+                               sweep_left_partial_floats(c->dev, n, m));
+    take(pf + 1);                                                              // part
+    const size_t base_work = o.size();
+    take((size_t)n * p); take((size_t)p * m); take((size_t)n * p); take((size_t)p * m);   // Gb Fb Gb2 Fb2
+    take(NL); take((size_t)l * m); take(NL); take(ML);                         // XRb XLb QLb QRb
+    take((size_t)l * p); take((size_t)p * l); take((size_t)p * p);             // GL FR W
+    const int64_t nm = std::max(n, m);
+    take((size_t)nm * p); take((size_t)nm * p); take((size_t)p * p);           // Bsub Bb Wb
+    take((size_t)l * p); take((size_t)p * l); take(32);                        // GLb FRb v
+    const size_t o_L = ar.take<double>(1);
+    take((size_t)(kMaxK + 1) * nm * 32);                                       // Zs
+    take((size_t)kMaxK * nm * p); take((size_t)kMaxK * nm * p);               // Ys Vb
+    const size_t o_lp = ar.take<double>(nb(nm, kThreads));
+    take((size_t)n * r); take((size_t)m * r);                                  // U V
+    take(NL); take(ML); take(NL); take(ML);                                    // Tn Tm Tn2 Tm2
+    take((size_t)l * l); take((size_t)l * l); take((size_t)l * l); take((size_t)l * l);
+    for (int k = 0; k < q; ++k) { take(NL); take(ML); }                        // QLb_k QRtb_k
+    if (hipMalloc((void**)&t->mem, ar.off) != hipSuccess) {
+        delete t;
+        return CNMF_ENOMEM;
+    }
+    t->bytes = ar.off;
+    auto F = [&](size_t i) { return reinterpret_cast<float*>(t->mem + o[i]); };
+    size_t i = 0;
+    t->oRt = F(i++);
+    t->oLT = F(i++);
+    t->A.resize(q + 1); t->QL.resize(q + 1); t->Cn.resize(q + 1); t->QtRt.resize(q + 1);
+    for (int k = 0; k <= q; ++k) { t->A[k] = F(i++); t->QL[k] = F(i++); t->Cn[k] = F(i++); t->QtRt[k] = F(i++); }
+    t->Bm.resize(q + 1); t->QRt.resize(q + 1); t->Cm.resize(q + 1); t->QtL.resize(q + 1);
+    for (int k = 0; k <= q; ++k) { t->Bm[k] = F(i++); t->QRt[k] = F(i++); t->Cm[k] = F(i++); t->QtL[k] = F(i++); }
+    t->QRtT.resize(q + 1); t->QtLT.resize(q + 1);
+    for (int k = 0; k <= q; ++k) { t->QRtT[k] = F(i++); t->QtLT[k] = F(i++); }
+    t->XL = F(i++);
+    for (int k = 0; k < nck; ++k) { t->Gc.push_back(F(i++)); t->Fc.push_back(F(i++)); }
+    t->Gh = F(i++);
+    t->Fh = F(i++);
+    t->replay = reinterpret_cast<int32_t*>(t->mem + o_rep);
+    t->part = F(i++);
+    if (i != base_work) { cnmf_tape_destroy(t); return CNMF_EINVAL; }
+    t->Gb = F(i++); t->Fb = F(i++); t->Gb2 = F(i++); t->Fb2 = F(i++);
+    t->XRb = F(i++); t->XLb = F(i++); t->QLb = F(i++); t->QRb = F(i++);
+    t->GL = F(i++); t->FR = F(i++); t->W = F(i++);
+    t->Bsub = F(i++); t->Bb = F(i++); t->Wb = F(i++);
+    t->GLb = F(i++); t->FRb = F(i++); t->v = F(i++);
+    t->L = reinterpret_cast<double*>(t->mem + o_L);
+    t->Zs = F(i++);
+    t->Ys = F(i++); t->Vb = F(i++);
+    t->Lpart = reinterpret_cast<double*>(t->mem + o_lp);
+    t->U = F(i++); t->V = F(i++);
+    t->Tn = F(i++); t->Tm = F(i++); t->Tn2 = F(i++); t->Tm2 = F(i++);
+    t->Rl = F(i++); t->Ril = F(i++); t->Ml = F(i++); t->Cl = F(i++);
+    for (int k = 0; k < q; ++k) { t->QLb_k.push_back(F(i++)); t->QRtb_k.push_back(F(i++)); }
+    const Dev& d = c->dev;
+    const uint64_t kk = (uint64_t)(uint32_t)t->K;
+    int rc = CNMF_OK;
+    if (fill_u64(d, reinterpret_cast<uint64_t*>(t->replay), T, kk | (kk << 32)) != hipSuccess)
+        rc = CNMF_EHIP;
+    if (!rc) rc = rsi_forward(t);
+    // outer loop with checkpoints every ckpt iterations
+    if (!rc && (hipMemcpyAsync(t->Gc[0], G0, (size_t)n * p * 4, hipMemcpyDeviceToDevice, d.stream) != hipSuccess ||
+                hipMemcpyAsync(t->Fc[0], F0, (size_t)p * m * 4, hipMemcpyDeviceToDevice, d.stream) != hipSuccess ||
+                hipMemcpyAsync(G_out, G0, (size_t)n * p * 4, hipMemcpyDeviceToDevice, d.stream) != hipSuccess ||
+                hipMemcpyAsync(F_out, F0, (size_t)p * m * 4, hipMemcpyDeviceToDevice, d.stream) != hipSuccess))
+        rc = CNMF_EHIP;
+    for (int s = 0; !rc && s * ckpt < T; ++s) {
+        const int cnt = std::min(ckpt, T - s * ckpt);
+        rc = solve_span(t, G_out, F_out, s * ckpt, cnt, false);
+        if (!rc && s + 1 < nck &&
+            (hipMemcpyAsync(t->Gc[s + 1], G_out, (size_t)n * p * 4, hipMemcpyDeviceToDevice, d.stream) != hipSuccess ||
+             hipMemcpyAsync(t->Fc[s + 1], F_out, (size_t)p * m * 4, hipMemcpyDeviceToDevice, d.stream) != hipSuccess))
+            rc = CNMF_EHIP;
+    }
+    if (rc) {
+        cnmf_tape_destroy(t);
+        return rc;
+    }
+    *tape_out = t;
+    return CNMF_OK;
+}
+
+int cnmf_adj_backward(cnmf_tape* t, const float* dG, const float* dF, float* dX, int64_t lddx,
+                      float* dG0, float* dF0) {
+    if (!t || bad_ptr(dG) || bad_ptr(dF) || bad_ptr(dX) || lddx < t->m) return CNMF_EINVAL;
+    cnmf_ctx* c = t->c;
+    if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
+    const Dev& d = c->dev;
+    const int64_t n = t->n, m = t->m;
+    const int p = t->p, l = t->l, T = t->T, ck = t->ck;
+    CK(copy2d(d, n, p, dG, p, t->Gb, p));
+    CK(copy2d(d, p, m, dF, m, t->Fb, m));
+    CK(fillf(d, (int64_t)n * l, 0.f, t->XRb));
+    CK(fillf(d, (int64_t)l * m, 0.f, t->XLb));
+    CK(fillf(d, (int64_t)n * l, 0.f, t->QLb));
+    CK(fillf(d, (int64_t)m * l, 0.f, t->QRb));
+    const int nseg = (T + ck - 1) / ck;
+    for (int s = nseg - 1; s >= 0; --s) {
+        const int t0 = s * ck, cnt = std::min(ck, T - t0);
+        // recompute the segment from its checkpoint, keeping every iterate
+        CK(hipMemcpyAsync(t->Tn, t->Gc[s], (size_t)n * p * 4, hipMemcpyDeviceToDevice, d.stream));
+        CK(hipMemcpyAsync(t->Tm, t->Fc[s], (size_t)p * m * 4, hipMemcpyDeviceToDevice, d.stream));
+        int rc = solve_span(t, t->Tn, t->Tm, t0, cnt, true);
+        if (rc) return rc;
+        for (int j = cnt - 1; j >= 0; --j) {
+            const float* Gcur = t->Gh + (size_t)j * n * p;
+            const float* Gprev = j > 0 ? t->Gh + (size_t)(j - 1) * n * p : t->Gc[s];
+            const float* Fprev = j > 0 ? t->Fh + (size_t)(j - 1) * p * m : t->Fc[s];
+            rc = outer_adj(t, Gprev, Fprev, Gcur);
+            if (rc) return rc;
+        }
+    }
+    if (dG0) CK(copy2d(d, n, p, t->Gb, p, dG0, p));
+    if (dF0) CK(copy2d(d, p, m, t->Fb, m, dF0, m));
+    const int rc = rsi_adj(t);
+    if (rc) return rc;
+    const int r = 2 * (2 * t->q + 1) * l;
+    dim3 grid(nb(m, 64), nb(n, 64));
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(kThreads), 0, d.stream, n, m, r, t->U, t->V, dX, lddx);
+    return from_hip(hipGetLastError());
+}
+
+int cnmf_tape_destroy(cnmf_tape* t) {
+    if (!t) return CNMF_OK;
+    if (t->c) {
+        (void)hipSetDevice(t->c->dev.device);
+        (void)hipStreamSynchronize(t->c->dev.stream);
+    }
+    if (t->mem) (void)hipFree(t->mem);
+    delete t;
+    return CNMF_OK;
+}
+
+int cnmf_tape_bytes(const cnmf_tape* t, uint64_t* bytes) {
+    if (!t || !bytes) return CNMF_EINVAL;
+    *bytes = t->bytes;
+    return CNMF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+"""Differentiation form: the hand-written adjoint of unrolled compressed
+NeNMF (through RSI, projections, momentum and L = lambda_max) against the
+FP64 CPU reference gradient (torch autograd through an independent FP64
+implementation) and against central differences of the GPU forward."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+cnmf = pytest.importorskip("paper_1812_04315_amd")
+
+
+def _case(n, m, p, nu, seed):
+    inst = synth.instance(n, m, p, nu, seed=seed, snr_db=30.0)
+    rng = np.random.default_rng(seed + 99)
+    Gt = rng.random(inst.G0.shape).astype(np.float32)
+    Ft = rng.random(inst.F0.shape).astype(np.float32)
+    return inst, Gt, Ft
+
+
+def _gpu_loss_grad(inst, Gt, Ft, q, T, K, ckpt):
+    import torch
+    X = dev(inst.X, (inst.X.shape[1] + 3) // 4 * 4)
+    G, F, tape = cnmf.adj_forward(X, dev(inst.omega_L), dev(inst.omega_R), dev(inst.G0),
+                                  dev(inst.F0), p=inst.p, nu=inst.ell - inst.p, q=q,
+                                  outer_iters=T, inner_steps=K, ckpt=ckpt)
+    dG = 2 * (G - dev(Gt))
+    dF = 2 * (F - dev(Ft))
+    dX, dG0, dF0 = tape.backward(dG, dF)
+    cnmf.check()
+    Lv = float(torch.sum((G - dev(Gt)) ** 2) + torch.sum((F - dev(Ft)) ** 2))
+    tape.close()
+    return Lv, host(dX), host(dG0), host(dF0), host(G), host(F)
+
+
+@pytest.mark.parametrize("n,m,p,nu,q,T,K,ckpt", [(60, 45, 3, 5, 2, 3, 5, 2),
+                                                 (200, 150, 5, 10, 2, 6, 5, 4),
+                                                 (300, 260, 10, 10, 2, 10, 5, 10)])
+def test_adjoint_matches_fp64_reference(n, m, p, nu, q, T, K, ckpt):
+    say("adjoint_ref", n, m, p, nu, q, T, K, ckpt)
+    inst, Gt, Ft = _case(n, m, p, nu, seed=n)
+    Lg, gX, gG, gF, G, F = _gpu_loss_grad(inst, Gt, Ft, q, T, K, ckpt)
+    Lr, rX, rG, rF = oracle.adjoint.loss_grad(inst.X, inst.omega_L, inst.omega_R, inst.G0,
+                                              inst.F0, Gt, Ft, q, T, K)
+    assert abs(Lg - Lr) <= 1e-3 * Lr
+    for g, r in ((gX, rX), (gG, rG), (gF, rF)):
+        cos = float(np.sum(g * r) / (np.linalg.norm(g) * np.linalg.norm(r)))
+        rel = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+        assert cos >= 0.999 and rel <= 1e-2, (cos, rel)
+
+
+def test_adjoint_matches_gpu_central_differences():
+    """32 random directions D (||D|| = ||X||), h = 1e-3: the directional
+    derivative <dL/dX, D> against (L(X + hD) - L(X - hD)) / 2h of the GPU
+    forward itself."""
+    say("adjoint_fd")
+    import torch
+    n, m, p, nu, q, T, K = 200, 150, 5, 10, 2, 6, 5
+    inst, Gt, Ft = _case(n, m, p, nu, seed=11)
+    Lv, gX, _, _, _, _ = _gpu_loss_grad(inst, Gt, Ft, q, T, K, 3)
+    rng = np.random.default_rng(5)
+    X = inst.X.astype(np.float64)
+    h = 1e-3
+    fd, an = [], []
+    for _ in range(32):
+        D = rng.standard_normal(X.shape)
+        D *= np.linalg.norm(X) / np.linalg.norm(D)
+        vals = []
+        for s in (1.0, -1.0):
+            Xs = (X + s * h * D).astype(np.float32)
+            G, F, tape = cnmf.adj_forward(dev(Xs, 152), dev(inst.omega_L), dev(inst.omega_R),
+                                          dev(inst.G0), dev(inst.F0), p=p, nu=nu, q=q,
+                                          outer_iters=T, inner_steps=K, ckpt=3)
+            vals.append(float(torch.sum((G - dev(Gt)) ** 2) + torch.sum((F - dev(Ft)) ** 2)))
+            tape.close()
+        fd.append((vals[0] - vals[1]) / (2 * h))
+        an.append(float(np.sum(gX * D)))
+    fd, an = np.array(fd), np.array(an)
+    cos = float(fd @ an / (np.linalg.norm(fd) * np.linalg.norm(an)))
+    rel = float(np.linalg.norm(fd - an) / np.linalg.norm(fd))
+    assert cos >= 0.999 and rel <= 1e-2, (cos, rel)
+
+
+def test_autograd_function():
+    say("adjoint_autograd")
+    import torch
+    n, m, p, nu, q, T, K = 120, 100, 4, 6, 2, 4, 5
+    inst, Gt, Ft = _case(n, m, p, nu, seed=21)
+    X = dev(inst.X, 100).clone().requires_grad_(True)
+    G0 = dev(inst.G0).requires_grad_(True)
+    F0 = dev(inst.F0).requires_grad_(True)
+    G, F = cnmf.compressed_nenmf(X, G0, F0, dev(inst.omega_L), dev(inst.omega_R), p=p, nu=nu,
+                                 q=q, outer_iters=T, inner_steps=K, ckpt=2)
+    loss = torch.sum((G - dev(Gt)) ** 2) + torch.sum((F - dev(Ft)) ** 2)
+    loss.backward()
+    cnmf.check()
+    _, rX, rG, rF = oracle.adjoint.loss_grad(inst.X, inst.omega_L, inst.omega_R, inst.G0,
+                                             inst.F0, Gt, Ft, q, T, K)
+    for g, r in ((host(X.grad), rX), (host(G0.grad), rG), (host(F0.grad), rF)):
+        assert np.linalg.norm(g - r) <= 1e-2 * np.linalg.norm(r)
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    say("adjoint_ckpt")
+    inst, Gt, Ft = _case(150, 120, 4, 8, seed=31)
+    a = _gpu_loss_grad(inst, Gt, Ft, 2, 8, 5, 1)
+    b = _gpu_loss_grad(inst, Gt, Ft, 2, 8, 5, 8)
+    c = _gpu_loss_grad(inst, Gt, Ft, 2, 8, 5, 3)
+    for x, y in ((a, b), (a, c)):
+        assert np.array_equal(x[1], y[1])
