@@ -55,9 +55,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle sample on the host (0 disables)")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--form", choices=["headline", "bf16", "batched"], default="headline",
+    ap.add_argument("--form", choices=["headline", "bf16", "batched", "adjoint"],
+                    default="headline",
                     help="headline: compressed vs plain on the 10k x 10k instance; bf16: the "
-                         "precision form on 20000 x 8000; batched: 256 uneven instances")
+                         "precision form on 20000 x 8000 and 200 x 150; batched: 256 uneven "
+                         "instances; adjoint: dL/dX of 50 unrolled outer iterations on 2000 x 2000")
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the dominant sweep (and an X-sized device copy as the "
                          "counter reference) for hardware-counter runs")
@@ -244,6 +246,188 @@ def bench_batched(args, torch, cnmf, synth):
     print(json.dumps(out), flush=True)
 
 
+def _events(torch, k):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+
+
+def bench_bf16(args, torch, cnmf, synth):
+    """Precision form: X-sized sweeps in BF16 on the matrix cores against the
+    FP32 path, on 20000 x 8000 (p = 20, l = 30, 30 dB, q = 4, 200 outer
+    iterations) and on the 200 x 150 rank-5 instance (against the FP64
+    oracle)."""
+    import oracle
+    dev = torch.device("cuda:0")
+    out = {"metric": "precision form: RSI ms and final relative error, BF16 vs FP32 sweeps",
+           "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "bf16",
+           "data": "synthetic", "steps": args.steps, "warmup": args.warmup,
+           "vs_baseline": None, "scaling": "weak"}
+    n, m, p, nu, q, T = 20000, 8000, 20, 10, 4, 200
+    log(args, f"generating {n}x{m}")
+    inst = synth.instance(n, m, p, nu, seed=args.seed, snr_db=30.0)
+    ld = (m + 63) // 64 * 64
+    Xb = torch.zeros(n, ld, device=dev)
+    Xb[:, :m] = torch.from_numpy(inst.X).to(dev)
+    X = Xb[:, :m]
+    X16 = cnmf.to_bf16(X, ld)
+    oL = torch.from_numpy(inst.omega_L).to(dev)
+    oR = torch.from_numpy(inst.omega_R).to(dev)
+    ell = p + nu
+    res = {}
+    for name, fn in (("fp32", lambda o: cnmf.rsi(X, oL, oR, p, nu, q, out=o)),
+                     ("bf16", lambda o: cnmf.rsi_bf16(X16, oL, oR, p, nu, q, out=o))):
+        comp = (torch.empty(n, ell, device=dev), torch.empty(m, ell, device=dev),
+                torch.empty(ell, m, device=dev), torch.empty(n, ell, device=dev))
+        for _ in range(args.warmup):
+            fn(comp)
+        e = _events(torch, 2)
+        e[0].record()
+        for _ in range(args.steps):
+            fn(comp)
+        e[1].record()
+        torch.cuda.synchronize()
+        rsi_ms = e[0].elapsed_time(e[1]) / args.steps
+        G = torch.from_numpy(inst.G0).to(dev)
+        F = torch.from_numpy(inst.F0).to(dev)
+        cnmf.solve(G, F, compressed=comp, p=p, nu=nu, outer_iters=T, inner_max=args.inner_max)
+        cnmf.check()
+        err = float(cnmf.rre(X, G[None], F[None]).cpu()[0])
+        QL, XL = comp[0].double(), comp[2].double()
+        Xd = X.double()
+        cerr = float(torch.linalg.norm(Xd - QL @ XL) / torch.linalg.norm(Xd))
+        res[name] = {"rsi_ms": round(rsi_ms, 3), "rre_final": err, "compressed_err": cerr,
+                     "GF": (G.double() @ F.double())}
+    gf32, gf16 = res["fp32"].pop("GF"), res["bf16"].pop("GF")
+    rel_gf = float(torch.linalg.norm(gf16 - gf32) / torch.linalg.norm(gf32))
+    del gf32, gf16
+    log(args, "FP64 oracle RSI on the large instance")
+    r64 = oracle.rsi(inst.X, inst.omega_L, inst.omega_R, q)
+    Xh = inst.X.astype(np.float64)
+    cerr64 = float(np.linalg.norm(Xh - r64.Q_L @ r64.X_L) / np.linalg.norm(Xh))
+    # BF16 sweeps on the X-sized products at this size
+    Y = torch.empty(n, ell, device=dev)
+    AT = torch.randn(ell, m, device=dev)
+    Bp = torch.randn(n, ell, device=dev)
+    sw = {}
+    for nm_, f in (("right_bf16", lambda: cnmf.sweep_right_bf16(X16, AT, a_trans=True, out=Y)),
+                   ("left_bf16", lambda: cnmf.sweep_left_bf16(X16, Bp)),
+                   ("right_fp32", lambda: cnmf.sweep_right(X, AT, a_trans=True, out=Y)),
+                   ("left_fp32", lambda: cnmf.sweep_left(X, Bp))):
+        for _ in range(3):
+            f()
+        e = _events(torch, 2)
+        e[0].record()
+        for _ in range(20):
+            f()
+        e[1].record()
+        torch.cuda.synchronize()
+        us = e[0].elapsed_time(e[1]) / 20 * 1e3
+        byts = (2.0 if "bf16" in nm_ else 4.0) * n * m
+        sw[nm_] = {"us": round(us, 1), "gbs": round(byts / us / 1e3, 1)}
+    # the 200 x 150 rank-5 instance against the FP64 oracle
+    c1 = synth.instance(200, 150, 5, 10, seed=args.seed)
+    Xc = torch.from_numpy(c1.X).to(dev)
+    comp16 = cnmf.rsi_bf16(cnmf.to_bf16(Xc), torch.from_numpy(c1.omega_L).to(dev),
+                           torch.from_numpy(c1.omega_R).to(dev), 5, 10, 4)
+    G = torch.from_numpy(c1.G0).to(dev)
+    F = torch.from_numpy(c1.F0).to(dev)
+    cnmf.solve(G, F, compressed=comp16, p=5, nu=10, outer_iters=20, inner_max=10)
+    cnmf.check()
+    ref = oracle.nenmf(c1.X, c1.G0, c1.F0, 20, 10,
+                       compressed=oracle.rsi(c1.X, c1.omega_L, c1.omega_R, 4))
+    gf = G.double().cpu().numpy() @ F.double().cpu().numpy()
+    gf64 = ref.G @ ref.F
+    out.update({
+        "value": res["bf16"]["rsi_ms"],
+        "config": {"workload": "20000x8000, p=20, l=30, 30 dB, q=4, 200 outer, global bound 1e-3; "
+                               "and 200x150 rank 5, 20 outer x <= 10 inner"},
+        "large": {"fp32": res["fp32"], "bf16": res["bf16"], "compressed_err_fp64_oracle": cerr64,
+                  "gf_rel_diff_bf16_vs_fp32": rel_gf, "sweeps": sw},
+        "c1": {"gf_rel_err_vs_fp64_oracle": float(np.linalg.norm(gf - gf64) / np.linalg.norm(gf64)),
+               "rre_bf16": oracle.rre(c1.X, G.double().cpu().numpy(), F.double().cpu().numpy()),
+               "rre_fp64_oracle": oracle.rre(c1.X, ref.G, ref.F)},
+    })
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args, torch, cnmf, synth):
+    """Differentiation form: n = m = 2000, p = 10, l = 20, q = 2, 30 dB, 50
+    outer iterations x 5 inner steps, checkpoints every 10; loss
+    ||G - Gt||^2 + ||F - Ft||^2 with seeded targets."""
+    import oracle
+    dev = torch.device("cuda:0")
+    n = m = 2000
+    p, nu, q, T, K, ck = 10, 10, 2, 50, 5, 10
+    inst = synth.instance(n, m, p, nu, seed=args.seed, snr_db=30.0)
+    rng = np.random.default_rng(args.seed + 99)
+    Gt = rng.random(inst.G0.shape).astype(np.float32)
+    Ft = rng.random(inst.F0.shape).astype(np.float32)
+    X = torch.from_numpy(inst.X).to(dev)
+    oL = torch.from_numpy(inst.omega_L).to(dev)
+    oR = torch.from_numpy(inst.omega_R).to(dev)
+    G0 = torch.from_numpy(inst.G0).to(dev)
+    F0 = torch.from_numpy(inst.F0).to(dev)
+    Gtd, Ftd = torch.from_numpy(Gt).to(dev), torch.from_numpy(Ft).to(dev)
+
+    def fwd(Xin):
+        G, F, tape = cnmf.adj_forward(Xin, oL, oR, G0, F0, p=p, nu=nu, q=q, outer_iters=T,
+                                      inner_steps=K, ckpt=ck)
+        return G, F, tape
+
+    tf, tb = [], []
+    for it in range(args.warmup + args.steps):
+        e = _events(torch, 3)
+        e[0].record()
+        G, F, tape = fwd(X)
+        e[1].record()
+        dX, dG0, dF0 = tape.backward(2 * (G - Gtd), 2 * (F - Ftd))
+        e[2].record()
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            tf.append(e[0].elapsed_time(e[1]))
+            tb.append(e[1].elapsed_time(e[2]))
+        tape_bytes = tape.bytes
+        tape.close()
+    cnmf.check()
+    gX = dX.double().cpu().numpy()
+    log(args, "FP64 reference gradient (CPU)")
+    t0 = time.perf_counter()
+    Lr, rX, _, _ = oracle.adjoint.loss_grad(inst.X, inst.omega_L, inst.omega_R, inst.G0,
+                                            inst.F0, Gt, Ft, q, T, K)
+    t_ref = time.perf_counter() - t0
+    cos = float(np.sum(gX * rX) / (np.linalg.norm(gX) * np.linalg.norm(rX)))
+    rel = float(np.linalg.norm(gX - rX) / np.linalg.norm(rX))
+    log(args, "central differences on the GPU forward (32 directions)")
+    Xh = inst.X.astype(np.float64)
+    h = 1e-3
+    fd, an = [], []
+    for _ in range(32):
+        D = rng.standard_normal(Xh.shape)
+        D *= np.linalg.norm(Xh) / np.linalg.norm(D)
+        vals = []
+        for sgn in (1.0, -1.0):
+            G, F, tape = fwd(torch.from_numpy((Xh + sgn * h * D).astype(np.float32)).to(dev))
+            vals.append(float(torch.sum((G - Gtd) ** 2) + torch.sum((F - Ftd) ** 2)))
+            tape.close()
+        fd.append((vals[0] - vals[1]) / (2 * h))
+        an.append(float(np.sum(gX * D)))
+    fd, an = np.array(fd), np.array(an)
+    out = {
+        "metric": "differentiation form: ms for dL/dX of 50 unrolled outer iterations (2000x2000)",
+        "value": round(min(tf) + min(tb), 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "n=m=2000, p=10, l=20, q=2, 30 dB, 50 outer x 5 inner, "
+                               "checkpoints every 10, loss ||G-Gt||^2+||F-Ft||^2"},
+        "forward_ms": round(min(tf), 3), "backward_ms": round(min(tb), 3),
+        "tape_mb": round(tape_bytes / 2 ** 20, 2),
+        "vs_fp64_reference": {"cosine": cos, "rel_err": rel, "reference_cpu_s": round(t_ref, 2)},
+        "vs_gpu_central_fd": {"h": h, "directions": 32,
+                              "cosine": float(fd @ an / (np.linalg.norm(fd) * np.linalg.norm(an))),
+                              "rel_err": float(np.linalg.norm(fd - an) / np.linalg.norm(fd))},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -258,6 +442,10 @@ def main():
     torch.cuda.set_device(0)
     if args.form == "batched":
         return bench_batched(args, torch, cnmf, synth)
+    if args.form == "bf16":
+        return bench_bf16(args, torch, cnmf, synth)
+    if args.form == "adjoint":
+        return bench_adjoint(args, torch, cnmf, synth)
     dev = torch.device("cuda:0")
     n, m, p, nu, q, T = args.n, args.m, args.p, args.nu, args.q, args.outer
     ell = p + nu
