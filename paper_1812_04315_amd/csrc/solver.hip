@@ -62,6 +62,16 @@ __device__ __forceinline__ uint64_t slot_load(const uint64_t* p) {
     return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations (lgkmcnt) but not for its outstanding global loads, so a poll
+// of the exchange words issued earlier stays in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // vmcnt / expcnt untouched, lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
 // ---------------------------------------------------------------------------
 // lambda_max of a symmetric p x p matrix held in LDS as doubles (destroyed),
 // by one wavefront: Householder tridiagonalisation (lane i owns row i), then
@@ -331,7 +341,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     auto publish = [&](double v, int step) {
         v = wave_sum(v);
         if (lane == 0) s_red[wave] = v;
-        __syncthreads();
+        lds_barrier();
         if (threadIdx.x == 0) {
             const double tot = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
             const uint64_t bits = (uint64_t)__double_as_longlong(tot);
@@ -341,24 +351,54 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             slot_store(sl + 1, tag, (uint32_t)(bits & 0xffffffffu));
         }
     };
-    // grid total of step `step` (wave 0 polls; result broadcast through LDS)
-    auto collect = [&](int step) -> double {
+    // Poll words of step `step`, issued early by wave 0 (up to 256 workgroups,
+    // four per lane) and checked later by collect().
+    uint64_t pwA[4][2];
+    auto poll_issue = [&](int step, uint64_t (&pw)[4][2]) {
+        const uint64_t* base = a.slot_pg + (size_t)(step % NSLOT) * 256 * 2;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const unsigned i = lane + 64 * u;
+            const unsigned ic = i < nblk ? i : 0u;
+            pw[u][0] = slot_load(base + 2 * ic);
+            pw[u][1] = slot_load(base + 2 * ic + 1);
+        }
+    };
+    // grid total of step `step` (wave 0 polls; result broadcast through LDS);
+    // prefetched: start from the words poll_issue() loaded
+    auto collect = [&](int step, bool prefetched, const uint64_t (&pw)[4][2]) -> double {
         if (wave == 0) {
             const unsigned tag = (seq << 10) | ((unsigned)step & 1023u);
             const uint64_t* base = a.slot_pg + (size_t)(step % NSLOT) * 256 * 2;
             unsigned spins = 0;
             int to = 0;
             double t = 0.0;
+            bool first = prefetched;
             for (;;) {
                 int mine_ok = 1;
                 t = 0.0;
-                for (unsigned i = lane; i < nblk; i += 64) {
-                    const uint64_t w0 = slot_load(base + 2 * i);
-                    const uint64_t w1 = slot_load(base + 2 * i + 1);
-                    if ((unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag)
-                        t += __longlong_as_double((long long)((w0 << 32) | (w1 & 0xffffffffu)));
-                    else
-                        mine_ok = 0;
+                if (first) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const unsigned i = lane + 64 * u;
+                        if (i < nblk) {
+                            const uint64_t w0 = pw[u][0], w1 = pw[u][1];
+                            if ((unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag)
+                                t += __longlong_as_double((long long)((w0 << 32) | (w1 & 0xffffffffu)));
+                            else
+                                mine_ok = 0;
+                        }
+                    }
+                    first = false;
+                } else {
+                    for (unsigned i = lane; i < nblk; i += 64) {
+                        const uint64_t w0 = slot_load(base + 2 * i);
+                        const uint64_t w1 = slot_load(base + 2 * i + 1);
+                        if ((unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag)
+                            t += __longlong_as_double((long long)((w0 << 32) | (w1 & 0xffffffffu)));
+                        else
+                            mine_ok = 0;
+                    }
                 }
                 if (__all(mine_ok)) break;
                 __builtin_amdgcn_s_sleep(1);
@@ -376,7 +416,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 if (to) raise_status(ctl, CNMF_ST_TIMEOUT);
             }
         }
-        __syncthreads();
+        lds_barrier();
         return s_tot;
     };
 
@@ -394,7 +434,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
 #pragma unroll
         for (int t = 0; t < TILES; ++t) v += pg2_of(z[t], g[t]);
         publish(v, 0);
-        pg0 = collect(0);
+        pg0 = collect(0, false, pwA);
         if (s_flag) ok = false;
     }
 
@@ -431,6 +471,10 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         int stop_at = -1;
         int K = 1;
         for (; K <= kend; ++K) {
+            const int jst = K - DLAG;
+            const bool test = check && jst >= a.inner_min && jst <= kmax;
+            // the poll of step K - DLAG is in flight during this step's compute
+            if (test && wave == 0) poll_issue(jst, pwA);
             if (K <= kmax) {
                 float zn[TILES][NR], gn[TILES][NR];
 #pragma unroll
@@ -476,17 +520,14 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
 #pragma unroll
                         for (int i = 0; i < NR; ++i) zh[j][t][i] = zh[j - 1][t][i];
             }
-            if (check) {
-                const int jst = K - DLAG;
-                if (jst >= a.inner_min && jst <= kmax) {
-                    const double tot = collect(jst);
-                    if (s_flag) { ok = false; break; }
-                    if (!(tot == tot)) {
-                        if (blk == 0 && threadIdx.x == 0) raise_status(ctl, CNMF_ST_NONFINITE);
-                    } else if (sqrt(tot) <= tol) {
-                        stop_at = jst;
-                        break;
-                    }
+            if (test) {
+                const double tot = collect(jst, true, pwA);
+                if (s_flag) { ok = false; break; }
+                if (!(tot == tot)) {
+                    if (blk == 0 && threadIdx.x == 0) raise_status(ctl, CNMF_ST_NONFINITE);
+                } else if (sqrt(tot) <= tol) {
+                    stop_at = jst;
+                    break;
                 }
             }
         }
