@@ -428,6 +428,7 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
     const size_t o_BF = ar.take<float>(comp ? 1 : (size_t)m * p);
     const size_t o_sw = ar.take<float>(comp ? 1 : std::max(sweep_right_partial_floats(c->dev, n, m),
                                                             sweep_left_partial_floats(c->dev, n, m)));
+    const size_t o_eig = ar.take<double>(4 * kEigWords);   // {L, v} per side and parity
     rc = ensure_ws(c, ar.off);
     if (rc) return rc;
     if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
@@ -437,6 +438,8 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
     float* BG = at<float>(c, o_BG);
     float* BF = at<float>(c, o_BF);
     float* sw = at<float>(c, o_sw);
+    double* eig = at<double>(c, o_eig);
+    auto eig_at = [&](int side, int par) { return eig + (size_t)(2 * side + par) * kEigWords; };
     Control* ctl = c->ctl;
     const bool global = prm->stop_rule == CNMF_STOP_GLOBAL;
 
@@ -517,6 +520,8 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
         CK(run(a, false));
     }
     if (tr.ticks && T > 0) CK(fill_u64(d, tr.ticks + 1, T, 0));
+    // no warm start for the first subproblem of either side
+    CK(fill_u64(d, reinterpret_cast<uint64_t*>(eig), 4 * kEigWords, 0));
     for (int t = 0; t < T; ++t) {
         CK(bg());
         PhaseArgs a = ga;
@@ -527,6 +532,8 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
         if (tr.lips) a.L_out = tr.lips + 2 * t;
         if (tr.tols) a.tol_out = tr.tols + 2 * t;
         if (tr.G_hist) a.hist = tr.G_hist + (size_t)t * n * p;
+        a.eig_in = eig_at(0, (t + 1) & 1);
+        a.eig_out = eig_at(0, t & 1);
         CK(run(a, true));
         CK(bf());
         a = fa;
@@ -538,6 +545,8 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
         if (tr.tols) a.tol_out = tr.tols + 2 * t + 1;
         if (tr.F_hist) a.hist = tr.F_hist + (size_t)t * p * m;
         if (tr.ticks) a.tick_out = (unsigned long long*)(tr.ticks + 1 + t);
+        a.eig_in = eig_at(1, (t + 1) & 1);
+        a.eig_out = eig_at(1, t & 1);
         CK(run(a, false));
     }
     return CNMF_OK;

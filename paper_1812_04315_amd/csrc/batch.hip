@@ -61,6 +61,7 @@ struct cnmf_batch {
     std::vector<float*> pG, pF;         // per instance: partial products
     std::vector<double*> st;            // per instance: tol[2], pg2[2]
     std::vector<float*> Gs, Fs;         // per instance: scratch factors for tuning
+    double* eig = nullptr;              // per instance: {L, v} per side and parity, contiguous
     unsigned* epoch = nullptr;
     unsigned* done = nullptr;
     // schedules and launch arguments
@@ -202,6 +203,9 @@ std::vector<PhaseArgs> solve_args(const cnmf_batch* b, int tg, int tf, int T, in
                 if (forced >= 0) a.forced = forced;
                 else if (in.replay) a.forced_ptr = in.replay + 2 * t + side;
                 if (in.steps && !scratch) a.steps_out = in.steps + 2 * t + side;
+                double* eg = b->eig + (size_t)i * 4 * kEigWords;
+                a.eig_in = eg + (size_t)(2 * side + ((t + 1) & 1)) * kEigWords;
+                a.eig_out = eg + (size_t)(2 * side + (t & 1)) * kEigWords;
                 v[(size_t)(3 + 2 * t + side) * n + i] = a;
             }
         }
@@ -251,7 +255,10 @@ hipError_t enqueue(const cnmf_batch* b, const Dev& d, const PhaseArgs* args, int
                    const uint32_t* schedG, const uint32_t* schedF, int rG, int rF, int tg,
                    int tf, bool with_pg) {
     const size_t n = b->inst.size();
-    hipError_t e = launch(b, d, args, false, schedG, schedF, rG, rF, tg, tf);
+    // no warm start for the first subproblem of either side
+    hipError_t e = fill_u64(d, reinterpret_cast<uint64_t*>(b->eig), (int64_t)n * 4 * kEigWords, 0);
+    if (e != hipSuccess) return e;
+    e = launch(b, d, args, false, schedG, schedF, rG, rF, tg, tf);
     if (e != hipSuccess) return e;
     if (with_pg) {
         if ((e = launch(b, d, args + n, true, schedG, schedF, rG, rF, tg, tf)) != hipSuccess) return e;
@@ -470,6 +477,7 @@ int cnmf_batch_create(cnmf_ctx* c, const cnmf_instance* inst, int32_t count,
         ogs.push_back(ar.take<float>((size_t)in.n * in.p));
         ofs.push_back(ar.take<float>((size_t)in.p * in.m));
     }
+    const size_t o_eig = ar.take<double>((size_t)count * 4 * kEigWords);
     const size_t o_ep = ar.take<unsigned>(2);
     if (hipMalloc((void**)&b->mem, ar.off) != hipSuccess) { delete b; return CNMF_ENOMEM; }
     for (int i = 0; i < count; ++i) {
@@ -480,6 +488,7 @@ int cnmf_batch_create(cnmf_ctx* c, const cnmf_instance* inst, int32_t count,
         b->Gs.push_back(reinterpret_cast<float*>(b->mem + ogs[i]));
         b->Fs.push_back(reinterpret_cast<float*>(b->mem + ofs[i]));
     }
+    b->eig = reinterpret_cast<double*>(b->mem + o_eig);
     b->epoch = reinterpret_cast<unsigned*>(b->mem + o_ep);
     b->done = b->epoch + 1;
     const unsigned init[2] = {1u, 0u};

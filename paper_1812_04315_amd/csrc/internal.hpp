@@ -314,6 +314,8 @@ struct PhaseArgs {
     double* tol_init_from;   // with kind 1: tol = ratio*sqrt(pg2 + *tol_init_from) -> tol_init_out[0..1]
     double* tol_init_out;
     unsigned nblk;           // workgroups of this subproblem (batched launches)
+    const double* eig_in;    // {L, v[32]} of the previous subproblem of this side, or null
+    double* eig_out;         // {L, v[32]} of this subproblem (written by block 0), or null
     float* hist;
     unsigned long long* tick_out;
 };
@@ -336,6 +338,7 @@ bool phase_grid(const Dev& d, int64_t rows, int* tiles, unsigned* nblk);
 hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles);
 constexpr int kPgSlots = 10;   // slots per workgroup for projected-gradient partials
 constexpr size_t kSlotWords = 1024 + (size_t)kPgSlots * 256 * 2;
+constexpr int kEigWords = 33;   // {L, v[32]} per side and parity
 
 // misc kernels (small.hip)
 hipError_t write_tick(const Dev& d, unsigned long long* tick);

@@ -78,7 +78,7 @@ __device__ __forceinline__ void lds_barrier() {
 // Sturm-sequence multisection over 64 points per round.  Returns the value
 // on every lane.
 // ---------------------------------------------------------------------------
-__device__ double lambda_max_wave(double (*A)[33], int p, double* v, double* wv, double* dg,
+__device__ __forceinline__ double lambda_max_wave(double (*A)[33], int p, double* v, double* wv, double* dg,
                                   double* eo) {
     const int lane = threadIdx.x & 63;
     for (int k = 0; k + 2 < p; ++k) {
@@ -167,6 +167,123 @@ __device__ double lambda_max_wave(double (*A)[33], int p, double* v, double* wv,
 
 }  // namespace
 
+// Solve (W - sigma I) x = r for the symmetric W (FP64 in LDS, p <= P) by
+// Gaussian elimination without pivoting in FP32, one wavefront.  Lane i
+// keeps row i of the active part in registers as a window R[c] = M[i][k + c]
+// that shifts by one column per step k, so the pivot column is always R[0];
+// the pivot row goes through LDS (U, which also keeps the upper factor for
+// the back substitution).  Returns the number of negative pivots -- by
+// Sylvester's law of inertia the number of eigenvalues of W below sigma --
+// or -1 on a zero or non-finite pivot.  r (LDS, p entries) becomes x.
+// FP32 suffices for the count whenever sigma is separated from the
+// spectrum by much more than p eps32 ||W|| (the elimination of a definite
+// matrix is backward stable); x only needs to be a good direction.
+template <int P>
+__device__ __forceinline__ int shifted_solve(const double (*W)[33], double sigma, double* r, int p,
+                                             float (*U)[33]) {
+    const int lane = threadIdx.x & 63;
+    float R[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c)
+        R[c] = (lane < p && c < p) ? (float)(W[lane][c] - (lane == c ? sigma : 0.0)) : 0.f;
+    float ri = lane < p ? (float)r[lane] : 0.f;
+    float* rk = &U[32][0];   // reduced right-hand sides
+    int neg = 0;
+    bool bad = false;
+    for (int k = 0; k < p; ++k) {
+        if (lane == k) {
+#pragma unroll
+            for (int c = 0; c < P; ++c) U[k][c] = R[c];
+            rk[k] = ri;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const float d = U[k][0];
+        neg += d < 0.f;
+        if (!(d != 0.f) || !(fabsf(d) < 1e37f)) bad = true;
+        const float inv = 1.f / ((d != 0.f && fabsf(d) < 1e37f) ? d : 1e-37f);
+        const float f = (lane > k && lane < p) ? R[0] * inv : 0.f;
+        ri = fmaf(-f, rk[k], ri);
+#pragma unroll
+        for (int c = 0; c < P - 1; ++c) R[c] = fmaf(-f, U[k][c + 1], R[c + 1]);
+        R[P - 1] = 0.f;
+        __builtin_amdgcn_wave_barrier();
+    }
+    // back substitution, x_k = (r_k - sum_{c >= 1} U[k][c] x_{k+c}) / U[k][0]:
+    // once x_k is known, every lane i < k removes its term
+    float xi = 0.f;
+    float acc = lane < p ? rk[lane] : 0.f;
+    for (int k = p - 1; k >= 0; --k) {
+        const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), k)) / U[k][0];
+        if (lane == k) xi = xk;
+        if (lane < k) acc = fmaf(-U[lane][k - lane], xk, acc);
+    }
+    if (lane < p) r[lane] = (double)xi;
+    __builtin_amdgcn_wave_barrier();
+    return bad ? -1 : neg;
+}
+
+// v^T W v / v^T v (W symmetric in LDS), on every lane.
+__device__ __forceinline__ double rayleigh(const double (*W)[33], const double* v, int p) {
+    const int lane = threadIdx.x & 63;
+    double wv = 0.0, vi = 0.0;
+    if (lane < p) {
+        vi = v[lane];
+        for (int j = 0; j < p; ++j) wv = fma(W[lane][j], v[j], wv);
+    }
+    const double num = wave_sum(vi * wv);
+    const double den = wave_sum(vi * vi);
+    return num / den;
+}
+
+__device__ __forceinline__ void normalise(double* v, int p) {
+    const int lane = threadIdx.x & 63;
+    const double nn = wave_sum(lane < p ? v[lane] * v[lane] : 0.0);
+    if (lane < p) v[lane] = (nn > 0.0 && nn < 1e300) ? v[lane] / sqrt(nn) : 0.0;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// lambda_max of the symmetric W (FP64, LDS) by one wavefront, warm-started
+// from the top eigenvector of the previous subproblem of the same side
+// (prev = {L, v[0..p)}; prev[0] <= 0 means none).  With rho0 the Rayleigh
+// quotient of the start vector (a lower bound), one factorisation of
+// W - sigma I, sigma = rho0 (1 + 1e-4), certifies by its inertia that every
+// eigenvalue lies below sigma and gives one inverse-iteration step with
+// that shift; the Rayleigh quotient of the result is L (between rho0 and
+// sigma, and within ~theta^2 of lambda_max for the remaining angle theta).
+// Without a usable start, or when the certificate fails, the
+// tridiagonalisation and bisection above give L and one inverse-iteration
+// step gives the vector.  On return v holds the unit top eigenvector.
+template <int P>
+__device__ __forceinline__ double lambda_max_warm(const double (*W)[33], double (*M)[33], double* v,
+                                                  int p, const double* prev, double* wv,
+                                                  double* dg, double* eo, double* tv) {
+    float (*U)[33] = reinterpret_cast<float (*)[33]>(&M[0][0]);   // 33 x 33 floats fit
+    const int lane = threadIdx.x & 63;
+    if (prev && prev[0] > 0.0) {
+        if (lane < p) v[lane] = prev[1 + lane];
+        __builtin_amdgcn_wave_barrier();
+        const double rho0 = rayleigh(W, v, p);
+        if (rho0 > 0.0 && rho0 < 1e300) {
+            const int cnt = shifted_solve<P>(W, rho0 * (1.0 + 1e-4), v, p, U);
+            normalise(v, p);
+            const double rho = rayleigh(W, v, p);
+            if (cnt == p && rho >= rho0 * (1.0 - 1e-12) && rho < 1e300) return rho;
+        }
+    }
+    for (int e = lane; e < p * p; e += 64) M[e / p][e % p] = W[e / p][e % p];
+    __builtin_amdgcn_wave_barrier();
+    const double L = lambda_max_wave(M, p, tv, wv, dg, eo);
+    if (lane < p) v[lane] = 1.0;
+    __builtin_amdgcn_wave_barrier();
+    if (L > 0.0 && L < 1e300) {
+        shifted_solve<P>(W, L * (1.0 + 1e-5), v, p, U);
+        normalise(v, p);
+    } else if (lane < p) {
+        v[lane] = 0.0;
+    }
+    return L;
+}
+
 namespace {
 
 // One subproblem (G rows or F columns) on workgroup blk of nblk; seq tags
@@ -181,6 +298,8 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     __shared__ float sW[32][33];      // W (p x p)
     __shared__ double sA[32][33];     // FP64 W for lambda_max
     __shared__ double sv[32], swv[32], sdg[32], seo[32];
+    __shared__ double sM[32][33];     // work matrix of the eigenvalue solver
+    __shared__ double sev[32];        // top eigenvector
     __shared__ double s_red[4];
     __shared__ double s_tot;
     __shared__ double s_L;
@@ -260,8 +379,12 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 sA[i][j] = 0.5 * ((double)sW[i][j] + (double)sW[j][i]);
             }
             __builtin_amdgcn_wave_barrier();
-            const double lm = lambda_max_wave(sA, p, sv, swv, sdg, seo);
+            const double lm = lambda_max_warm<16 * PT>(sA, sM, sev, p, a.eig_in, swv, sdg, seo, sv);
             if (lane == 0) s_L = lm;
+            if (a.eig_out && blk == 0) {
+                if (lane == 0) a.eig_out[0] = (lm > 0.0 && lm == lm) ? lm : 0.0;
+                if (lane < p) a.eig_out[1 + lane] = sev[lane];
+            }
         }
     }
 
