@@ -84,7 +84,7 @@ int cnmf_create(cnmf_ctx** out, int device, void* stream) {
     }
     if (const char* e = std::getenv("CNMF_DLAG")) {
         const int v = std::atoi(e);
-        if (v >= 0 && v <= 4) c->dlag = v;
+        if ((v >= 0 && v <= 4) || v == kGrouped) c->dlag = v;
     }
     *out = c;
     return CNMF_OK;

@@ -17,7 +17,7 @@ struct cnmf_ctx {
     uint64_t* slots = nullptr;    // device, tagged exchange words of the phase kernels
     uint64_t* oxch = nullptr;     // device, tagged exchange words of the orthonormalisation
     unsigned seq = 0;             // last tag used
-    int dlag = 2;                 // steps between a norm and its stopping test
+    int dlag = -1;                // stop-test lag (-1: automatic, see the phase launcher)
     char* ws = nullptr;           // device workspace
     size_t ws_bytes = 0;
     double clock_hz = 1e8;

@@ -108,6 +108,26 @@ __device__ __forceinline__ double wave_sum(double v) {
     return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
+// Four wavefront sums at once: lane L returns the total over the wavefront of
+// v[quad_slot(L)].  Quad exchanges leave one partial of each of the four
+// values per quad, row rotations by 8 then 4 and lane exchanges across 16 and
+// 32 finish the sum; each step adds two operands that the partner lane adds in
+// the other order, so all lanes with the same slot hold the same bits.
+__device__ __forceinline__ int quad_slot(int lane) { return 2 * (lane & 1) + ((lane >> 1) & 1); }
+__device__ __forceinline__ double wave_sum4(const double (&v)[4]) {
+    const int lane = threadIdx.x & 63;
+    const bool odd = lane & 1;
+    const double a0 = (odd ? v[2] : v[0]) + dpp_d<kDppXor1>(odd ? v[0] : v[2]);
+    const double a1 = (odd ? v[3] : v[1]) + dpp_d<kDppXor1>(odd ? v[1] : v[3]);
+    const bool hi = (lane >> 1) & 1;
+    double b = (hi ? a1 : a0) + dpp_d<kDppXor2>(hi ? a0 : a1);
+    b += dpp_d<kDppRor8>(b);
+    b += dpp_d<kDppRor4>(b);
+    b += __shfl_xor(b, 16);
+    b += __shfl_xor(b, 32);
+    return b;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
     v += dpp_f<kDppXor1>(v);
     v += dpp_f<kDppXor2>(v);
@@ -294,7 +314,7 @@ struct PhaseArgs {
     int nin;
     float* part_out;         // [nblk][32][32] (may be null)
     uint64_t* slot_s;        // [1024] S exchange
-    uint64_t* slot_pg;       // [kMaxSlot][256][2] projected-gradient exchange
+    uint64_t* slot_pg;       // kPgWords projected-gradient exchange words
     unsigned seq;            // launch sequence (tag), 1 .. 2^22 - 1
     Control* ctl;
     // stopping
@@ -337,7 +357,9 @@ hipError_t phase_batched(const Dev& d, const BatchLaunch& b, int tiles, int dlag
 bool phase_grid(const Dev& d, int64_t rows, int* tiles, unsigned* nblk);
 hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles);
 constexpr int kPgSlots = 10;   // slots per workgroup for projected-gradient partials
-constexpr size_t kSlotWords = 1024 + (size_t)kPgSlots * 256 * 2;
+constexpr size_t kPgWords = 8192;   // projected-gradient exchange words
+constexpr size_t kSlotWords = 1024 + kPgWords;
+constexpr int kGrouped = 8;     // stop-test lag value selecting the grouped exchange
 constexpr int kEigWords = 33;   // {L, v[32]} per side and parity
 
 // misc kernels (small.hip)

@@ -222,13 +222,21 @@ __device__ __forceinline__ int shifted_solve(const double (*W)[33], double sigma
     return bad ? -1 : neg;
 }
 
-// v^T W v / v^T v (W symmetric in LDS), on every lane.
+// v^T W v / v^T v (W symmetric in LDS, p <= P), on every lane.
+template <int P>
 __device__ __forceinline__ double rayleigh(const double (*W)[33], const double* v, int p) {
     const int lane = threadIdx.x & 63;
     double wv = 0.0, vi = 0.0;
     if (lane < p) {
         vi = v[lane];
-        for (int j = 0; j < p; ++j) wv = fma(W[lane][j], v[j], wv);
+        double t[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) t[j] = j < p ? W[lane][j] * v[j] : 0.0;
+#pragma unroll
+        for (int w = P / 2; w >= 1; w /= 2)
+#pragma unroll
+            for (int j = 0; j < w; ++j) t[j] += t[j + w];
+        wv = t[0];
     }
     const double num = wave_sum(vi * wv);
     const double den = wave_sum(vi * vi);
@@ -262,11 +270,11 @@ __device__ __forceinline__ double lambda_max_warm(const double (*W)[33], double 
     if (prev && prev[0] > 0.0) {
         if (lane < p) v[lane] = prev[1 + lane];
         __builtin_amdgcn_wave_barrier();
-        const double rho0 = rayleigh(W, v, p);
+        const double rho0 = rayleigh<P>(W, v, p);
         if (rho0 > 0.0 && rho0 < 1e300) {
             const int cnt = shifted_solve<P>(W, rho0 * (1.0 + 1e-4), v, p, U);
             normalise(v, p);
-            const double rho = rayleigh(W, v, p);
+            const double rho = rayleigh<P>(W, v, p);
             if (cnt == p && rho >= rho0 * (1.0 - 1e-12) && rho < 1e300) return rho;
         }
     }
@@ -291,9 +299,17 @@ namespace {
 template <int PT, int TILES, int DLAG>
 __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned blk,
                                            const unsigned nblk, const unsigned seq) {
-    constexpr int NH = (DLAG + 1) > 2 ? (DLAG + 1) : 2;     // iterates kept
+    // DLAG = kGrouped: the norms of GB consecutive steps travel in one
+    // exchange, tested one group late; otherwise every step's norm is
+    // exchanged and tested DLAG steps late.
+    constexpr bool GROUPED = DLAG == kGrouped;
+    constexpr int GB = 4;
+    constexpr int NH = GROUPED ? 2 : ((DLAG + 1) > 2 ? (DLAG + 1) : 2);   // iterates kept
     constexpr int NR = PT * 4;                              // registers per row tile
-    constexpr int NSLOT = 2 * DLAG + 2;
+    // exchanges in flight (grouped: a workgroup that publishes group h has
+    // tested group h - 1, so every workgroup has read group h - 2)
+    constexpr int NSLOT = GROUPED ? 4 : 2 * DLAG + 2;
+    static_assert((size_t)NSLOT * 256 * 2 * (GROUPED ? GB : 1) <= kPgWords, "exchange words");
     __shared__ float sS[32][33];      // S (rows: M index, cols: p)
     __shared__ float sW[32][33];      // W (p x p)
     __shared__ double sA[32][33];     // FP64 W for lambda_max
@@ -301,6 +317,9 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     __shared__ double sM[32][33];     // work matrix of the eigenvalue solver
     __shared__ double sev[32];        // top eigenvector
     __shared__ double s_red[4];
+    __shared__ double s_pub[2][4][GB];    // grouped, by group parity: wave sums of own norms
+    __shared__ double s_cons[2][4][GB];   //   wave sums of the polled norms
+    __shared__ int s_cok[2][4];           //   polled words all carried the group's tag
     __shared__ double s_tot;
     __shared__ double s_L;
     __shared__ int s_flag;
@@ -563,6 +582,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
 
     double tol = a.tol_ptr ? *a.tol_ptr : a.tol_value;
     if (a.ratio > 0.0 && a.kind == 0) tol = a.ratio * sqrt(pg0);
+    const double tol2 = tol >= 0.0 ? tol * tol : -1.0;   // the test is ||pg||^2 <= tol^2
     const int forced = a.forced_ptr ? (int)*a.forced_ptr : a.forced;
     const int kmax = (a.kind != 0) ? 0 : (forced >= 0 ? forced : a.inner_max);
     int steps = 0;
@@ -575,7 +595,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         for (int t = 0; t < TILES; ++t)
 #pragma unroll
             for (int i = 0; i < NR; ++i) zh[j][t][i] = z[t][i];
-    int out_idx = 0;
+    int out_idx = GROUPED ? -1 : 0;   // the grouped loop writes z itself
 
     if (!(L > 0.0)) {
         if (a.kind == 0 && blk == 0 && threadIdx.x == 0)
@@ -590,9 +610,196 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         double alpha = 1.0;
         float beta = 0.f;
         const bool check = forced < 0;
-        const int kend = check ? kmax + DLAG : kmax;
         int stop_at = -1;
         int K = 1;
+        int kend = kmax;
+        if constexpr (GROUPED) {
+            // Steps run in groups of GB: group gi holds steps GB (gi-1) + 1 .. GB gi.
+            // The norm of step K - 1 is formed while the products of step K run.
+            // A group's norms are published together at the first step of the
+            // next group, polled at its second step and tested at its last, so
+            // a stop at step s is seen at most 2 GB - 1 steps later; the
+            // iterates of the group under test are kept for the return value.
+            static_assert(GB == 4, "four norms per exchange");
+            const int glast = (kmax + GB - 1) / GB;
+            const int gend = check ? glast + 1 : glast;
+            const int q = quad_slot(lane);            // step of a group this lane reduces
+            float cur[GB][TILES][NR], sav[GB][TILES][NR], gb2[2][TILES][NR];
+            double pgv[GB];
+            uint64_t pw[4][2];
+#pragma unroll
+            for (int u = 0; u < GB; ++u) {
+                pgv[u] = 0.0;
+#pragma unroll
+                for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                    for (int i = 0; i < NR; ++i) sav[u][t][i] = z[t][i];
+            }
+#pragma unroll
+            for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                for (int i = 0; i < NR; ++i) gb2[0][t][i] = gb2[1][t][i] = g[t][i];
+            auto testable = [&](int gc) { return gc >= 1 && gc * GB >= a.inner_min; };
+            auto poll_group = [&](int gc) {
+                const uint64_t* base = a.slot_pg + (size_t)(gc % NSLOT) * 256 * (2 * GB) + 2 * q;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const unsigned i = (unsigned)(wave * 64 + 16 * j + (lane >> 2));
+                    const unsigned ic = i < nblk ? i : 0u;
+                    pw[j][0] = slot_load(base + (size_t)ic * (2 * GB));
+                    pw[j][1] = slot_load(base + (size_t)ic * (2 * GB) + 1);
+                }
+            };
+            auto publish_group = [&](int gc) {
+                const double r = wave_sum4(pgv);
+                if (lane < GB) s_pub[gc & 1][wave][q] = r;
+                lds_barrier();
+                if (threadIdx.x < GB) {
+                    const int uu = threadIdx.x;
+                    const double tot = (s_pub[gc & 1][0][uu] + s_pub[gc & 1][1][uu]) +
+                                       (s_pub[gc & 1][2][uu] + s_pub[gc & 1][3][uu]);
+                    const uint64_t bits = (uint64_t)__double_as_longlong(tot);
+                    const unsigned tag = (seq << 10) | ((unsigned)gc & 1023u);
+                    uint64_t* sl = a.slot_pg + ((size_t)(gc % NSLOT) * 256 + blk) * (2 * GB) + 2 * uu;
+                    slot_store(sl, tag, (uint32_t)(bits >> 32));
+                    slot_store(sl + 1, tag, (uint32_t)(bits & 0xffffffffu));
+                }
+            };
+            // grid totals of group gc's norms; false on time-out
+            auto consume_group = [&](int gc, double (&tot)[GB]) -> bool {
+                const unsigned tag = (seq << 10) | ((unsigned)gc & 1023u);
+                const int par = gc & 1;
+                for (unsigned spins = 0;; ++spins) {
+                    int okl = 1;
+                    double pj[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const unsigned i = (unsigned)(wave * 64 + 16 * j + (lane >> 2));
+                        const uint64_t w0 = pw[j][0], w1 = pw[j][1];
+                        const bool good = (unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag;
+                        pj[j] = (i < nblk && good)
+                                    ? __longlong_as_double((long long)((w0 << 32) | (w1 & 0xffffffffu)))
+                                    : 0.0;
+                        if (i < nblk && !good) okl = 0;
+                    }
+                    double r = (pj[0] + pj[1]) + (pj[2] + pj[3]);
+                    r += dpp_d<kDppRor8>(r);
+                    r += dpp_d<kDppRor4>(r);
+                    r += __shfl_xor(r, 16);
+                    r += __shfl_xor(r, 32);
+                    const int wok = __all(okl);
+                    if (lane < GB) s_cons[par][wave][q] = r;
+                    if (lane == 0) s_cok[par][wave] = wok;
+                    lds_barrier();
+                    if (s_cok[par][0] && s_cok[par][1] && s_cok[par][2] && s_cok[par][3]) {
+#pragma unroll
+                        for (int u = 0; u < GB; ++u)
+                            tot[u] = (s_cons[par][0][u] + s_cons[par][1][u]) +
+                                     (s_cons[par][2][u] + s_cons[par][3][u]);
+                        return true;
+                    }
+                    if (spins >= (kSpinLimit >> 4)) return false;   // uniform: every wave counts alike
+                    lds_barrier();   // every wave has read this round's partials
+                    __builtin_amdgcn_s_sleep(1);
+                    poll_group(gc);
+                }
+            };
+            bool done = false;
+            for (int gi = 1; gi <= gend && !done; ++gi) {
+#pragma unroll
+                for (int u = 0; u < GB; ++u) {
+                    K = GB * (gi - 1) + 1 + u;
+                    // Z_{K-1}, Z_{K-2} and their gradients
+                    float (&z1)[TILES][NR] = (u == 0) ? sav[GB - 1] : cur[(u + GB - 1) % GB];
+                    float (&z2)[TILES][NR] = (u == 0) ? sav[GB - 2] : (u == 1) ? sav[GB - 1] : cur[(u + GB - 2) % GB];
+                    float (&g1)[TILES][NR] = gb2[(u + 1) & 1];
+                    float (&g2)[TILES][NR] = gb2[u & 1];
+                    const bool live = K <= kmax;   // later steps repeat Z_kmax
+#pragma unroll
+                    for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                        for (int i = 0; i < NR; ++i) {
+                            const float y = fmaf(beta, z1[t][i] - z2[t][i], z1[t][i]);
+                            const float gy = fmaf(beta, g1[t][i] - g2[t][i], g1[t][i]);
+                            const float v = fmaf(-gy, invL, y);
+                            const float zn = (v > 0.f || v != v) ? v : 0.f;
+                            cur[u][t][i] = live ? zn : z1[t][i];
+                        }
+                    double pv = 0.0;   // norm of step K - 1
+#pragma unroll
+                    for (int t = 0; t < TILES; ++t) pv += pg2_of(z1[t], g1[t]);
+                    pgv[(u + GB - 1) % GB] = pv;
+#pragma unroll
+                    for (int t = 0; t < TILES; ++t) grad(cur[u][t], bb[t], g2[t]);
+                    const double alpha_n = 0.5 * (1.0 + sqrt(4.0 * alpha * alpha + 1.0));
+                    beta = (float)((alpha - 1.0) / alpha_n);
+                    alpha = alpha_n;
+                    if (!check) {
+                        if (K == kmax) {
+#pragma unroll
+                            for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                                for (int i = 0; i < NR; ++i) z[t][i] = cur[u][t][i];
+                            steps = kmax;
+                            done = true;
+                            break;
+                        }
+                        continue;
+                    }
+                    if (u == 0 && gi >= 2) publish_group(gi - 1);
+                    if (u == 1 && testable(gi - 1)) poll_group(gi - 1);
+                    if (u == GB - 1 && testable(gi - 1)) {
+                        const int gc = gi - 1;
+                        double tot[GB];
+                        if (!consume_group(gc, tot)) {
+                            if (threadIdx.x == 0) raise_status(ctl, CNMF_ST_TIMEOUT);
+                            ok = false;
+                            done = true;
+                            break;
+                        }
+                        int hit = -1;
+#pragma unroll
+                        for (int uu = 0; uu < GB; ++uu) {
+                            const int st = (gc - 1) * GB + 1 + uu;
+                            if (hit >= 0 || st < a.inner_min || st > kmax) continue;
+                            if (!(tot[uu] == tot[uu])) {
+                                if (blk == 0 && threadIdx.x == 0) raise_status(ctl, CNMF_ST_NONFINITE);
+                            } else if (tot[uu] <= tol2) {
+                                hit = uu;
+                            }
+                        }
+                        if (hit >= 0) {
+#pragma unroll
+                            for (int uu = 0; uu < GB; ++uu)
+                                if (uu == hit)
+#pragma unroll
+                                    for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                                        for (int i = 0; i < NR; ++i) z[t][i] = sav[uu][t][i];
+                            steps = (gc - 1) * GB + 1 + hit;
+                            done = true;
+                            break;
+                        }
+                    }
+                }
+                if (!done) {
+#pragma unroll
+                    for (int u = 0; u < GB; ++u)
+#pragma unroll
+                        for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                            for (int i = 0; i < NR; ++i) sav[u][t][i] = cur[u][t][i];
+                }
+            }
+            if (!done && ok) {   // budget spent without a stop: Z_kmax
+#pragma unroll
+                for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                    for (int i = 0; i < NR; ++i) z[t][i] = sav[GB - 1][t][i];
+                steps = kmax;
+            }
+        } else {
+        kend = check ? kmax + DLAG : kmax;
         for (; K <= kend; ++K) {
             const int jst = K - DLAG;
             const bool test = check && jst >= a.inner_min && jst <= kmax;
@@ -648,7 +855,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 if (s_flag) { ok = false; break; }
                 if (!(tot == tot)) {
                     if (blk == 0 && threadIdx.x == 0) raise_status(ctl, CNMF_ST_NONFINITE);
-                } else if (sqrt(tot) <= tol) {
+                } else if (tot <= tol2) {
                     stop_at = jst;
                     break;
                 }
@@ -656,7 +863,8 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         }
         if (K > kend) K = kend;
         steps = stop_at >= 0 ? stop_at : kmax;
-        out_idx = K - steps;   // 0 .. DLAG
+        out_idx = K - steps;   // 0 .. NH - 1
+        }
     }
 
     // final iterate zh[out_idx] -> z
@@ -776,9 +984,17 @@ hipError_t launch3(const Dev& d, const PhaseArgs& a, unsigned nblk) {
     return hipGetLastError();
 }
 
+// Stop-test lag: -1 picks the grouped exchange when the iterate history
+// fits the registers (PT * TILES <= 2), else a lag of two steps.
 template <int PT, int TILES>
 hipError_t launch2(const Dev& d, const PhaseArgs& a, unsigned nblk) {
-    switch (a.dlag) {
+    int dl = a.dlag;
+    if (dl < 0) dl = PT * TILES <= 2 ? kGrouped : 2;
+    if (dl == kGrouped) {
+        if constexpr (PT * TILES <= 2) return launch3<PT, TILES, kGrouped>(d, a, nblk);
+        dl = 2;
+    }
+    switch (dl) {
         case 0: return launch3<PT, TILES, 0>(d, a, nblk);
         case 1: return launch3<PT, TILES, 1>(d, a, nblk);
         case 2: return launch3<PT, TILES, 2>(d, a, nblk);
@@ -841,6 +1057,14 @@ __global__ __launch_bounds__(kThreads) void k_phase_batched(BatchLaunch b) {
 template <int TILES>
 hipError_t launch_batched2(const Dev& d, const BatchLaunch& b, int dlag) {
     dim3 grid((unsigned)b.slots), block(kThreads);
+    if (dlag < 0) dlag = TILES == 1 ? kGrouped : 2;
+    if (dlag == kGrouped) {
+        if constexpr (TILES == 1) {
+            hipLaunchKernelGGL((k_phase_batched<1, kGrouped>), grid, block, 0, d.stream, b);
+            return hipGetLastError();
+        }
+        dlag = 2;
+    }
     switch (dlag) {
         case 0: hipLaunchKernelGGL((k_phase_batched<TILES, 0>), grid, block, 0, d.stream, b); break;
         case 1: hipLaunchKernelGGL((k_phase_batched<TILES, 1>), grid, block, 0, d.stream, b); break;
@@ -868,7 +1092,7 @@ bool phase_grid(const Dev& d, int64_t rows, int* tiles, unsigned* nblk) {
 }
 
 hipError_t phase_batched(const Dev& d, const BatchLaunch& b, int tiles, int dlag) {
-    if (dlag < 0 || dlag > 4 || b.slots < 1) return hipErrorInvalidValue;
+    if (dlag < -1 || (dlag > 4 && dlag != kGrouped) || b.slots < 1) return hipErrorInvalidValue;
     switch (tiles) {
         case 1: return launch_batched2<1>(d, b, dlag);
         case 2: return launch_batched2<2>(d, b, dlag);
@@ -877,7 +1101,8 @@ hipError_t phase_batched(const Dev& d, const BatchLaunch& b, int tiles, int dlag
 }
 
 hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles) {
-    if (a.p < 1 || a.p > 32 || a.dlag < 0 || a.dlag > 4) return hipErrorInvalidValue;
+    if (a.p < 1 || a.p > 32 || a.dlag < -1 || (a.dlag > 4 && a.dlag != kGrouped))
+        return hipErrorInvalidValue;
     if (a.p <= 16) return launch1<1>(d, a, tiles, nblk);
     return launch1<2>(d, a, tiles, nblk);
 }
