@@ -167,127 +167,134 @@ __device__ __forceinline__ double lambda_max_wave(double (*A)[33], int p, double
 
 }  // namespace
 
-// Solve (W - sigma I) x = r for the symmetric W (FP64 in LDS, p <= P) by
-// Gaussian elimination without pivoting in FP32, one wavefront.  Lane i
-// keeps row i of the active part in registers as a window R[c] = M[i][k + c]
-// that shifts by one column per step k, so the pivot column is always R[0];
-// the pivot row goes through LDS (U, which also keeps the upper factor for
-// the back substitution).  Returns the number of negative pivots -- by
-// Sylvester's law of inertia the number of eigenvalues of W below sigma --
-// or -1 on a zero or non-finite pivot.  r (LDS, p entries) becomes x.
-// FP32 suffices for the count whenever sigma is separated from the
-// spectrum by much more than p eps32 ||W|| (the elimination of a definite
-// matrix is backward stable); x only needs to be a good direction.
+// The warm-started lambda_max below works on one wavefront with lane i < p
+// owning row i of the symmetric part of W in FP64 registers (wr) and entry i
+// of vectors; everything else is lane reads (no LDS round trips).
+
+// wr = row `lane` of (W + W^T) / 2 for W (p x p floats, row stride 33);
+// zero outside p x p.
 template <int P>
-__device__ __forceinline__ int shifted_solve(const double (*W)[33], double sigma, double* r, int p,
-                                             float (*U)[33]) {
+__device__ __forceinline__ void sym_row(const float (*W)[33], int p, double (&wr)[P]) {
     const int lane = threadIdx.x & 63;
-    float R[P];
+    const int i = lane < P ? lane : 0;
 #pragma unroll
-    for (int c = 0; c < P; ++c)
-        R[c] = (lane < p && c < p) ? (float)(W[lane][c] - (lane == c ? sigma : 0.0)) : 0.f;
-    float ri = lane < p ? (float)r[lane] : 0.f;
-    float* rk = &U[32][0];   // reduced right-hand sides
-    int neg = 0;
-    bool bad = false;
-    for (int k = 0; k < p; ++k) {
-        if (lane == k) {
-#pragma unroll
-            for (int c = 0; c < P; ++c) U[k][c] = R[c];
-            rk[k] = ri;
-        }
-        __builtin_amdgcn_wave_barrier();
-        const float d = U[k][0];
-        neg += d < 0.f;
-        if (!(d != 0.f) || !(fabsf(d) < 1e37f)) bad = true;
-        const float inv = 1.f / ((d != 0.f && fabsf(d) < 1e37f) ? d : 1e-37f);
-        const float f = (lane > k && lane < p) ? R[0] * inv : 0.f;
-        ri = fmaf(-f, rk[k], ri);
-#pragma unroll
-        for (int c = 0; c < P - 1; ++c) R[c] = fmaf(-f, U[k][c + 1], R[c + 1]);
-        R[P - 1] = 0.f;
-        __builtin_amdgcn_wave_barrier();
-    }
-    // back substitution, x_k = (r_k - sum_{c >= 1} U[k][c] x_{k+c}) / U[k][0]:
-    // once x_k is known, every lane i < k removes its term
-    float xi = 0.f;
-    float acc = lane < p ? rk[lane] : 0.f;
-    for (int k = p - 1; k >= 0; --k) {
-        const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), k)) / U[k][0];
-        if (lane == k) xi = xk;
-        if (lane < k) acc = fmaf(-U[lane][k - lane], xk, acc);
-    }
-    if (lane < p) r[lane] = (double)xi;
-    __builtin_amdgcn_wave_barrier();
-    return bad ? -1 : neg;
+    for (int j = 0; j < P; ++j)
+        wr[j] = (lane < p && j < p) ? 0.5 * ((double)W[i][j] + (double)W[j][i]) : 0.0;
 }
 
-// v^T W v / v^T v (W symmetric in LDS, p <= P), on every lane.
+// v^T W v / v^T v on every lane (lane i < p holds v_i; zero elsewhere).
 template <int P>
-__device__ __forceinline__ double rayleigh(const double (*W)[33], const double* v, int p) {
-    const int lane = threadIdx.x & 63;
-    double wv = 0.0, vi = 0.0;
-    if (lane < p) {
-        vi = v[lane];
-        double t[P];
+__device__ __forceinline__ double rayleigh(const double (&wr)[P], double v) {
+    double t0 = 0.0, t1 = 0.0;
 #pragma unroll
-        for (int j = 0; j < P; ++j) t[j] = j < p ? W[lane][j] * v[j] : 0.0;
-#pragma unroll
-        for (int w = P / 2; w >= 1; w /= 2)
-#pragma unroll
-            for (int j = 0; j < w; ++j) t[j] += t[j + w];
-        wv = t[0];
+    for (int j = 0; j < P; j += 2) {
+        t0 = fma(wr[j], lane_d(v, j), t0);
+        if (j + 1 < P) t1 = fma(wr[j + 1], lane_d(v, j + 1), t1);
     }
-    const double num = wave_sum(vi * wv);
-    const double den = wave_sum(vi * vi);
+    const double num = wave_sum(v * (t0 + t1));
+    const double den = wave_sum(v * v);
     return num / den;
 }
 
-__device__ __forceinline__ void normalise(double* v, int p) {
-    const int lane = threadIdx.x & 63;
-    const double nn = wave_sum(lane < p ? v[lane] * v[lane] : 0.0);
-    if (lane < p) v[lane] = (nn > 0.0 && nn < 1e300) ? v[lane] / sqrt(nn) : 0.0;
-    __builtin_amdgcn_wave_barrier();
+// v scaled to (about) unit length: only its direction is used
+__device__ __forceinline__ void normalise(double& v) {
+    const double nn = wave_sum(v * v);
+    v *= (nn > 0.0 && nn < 1e300) ? __builtin_amdgcn_rsq(nn) : 0.0;
 }
 
-// lambda_max of the symmetric W (FP64, LDS) by one wavefront, warm-started
-// from the top eigenvector of the previous subproblem of the same side
-// (prev = {L, v[0..p)}; prev[0] <= 0 means none).  With rho0 the Rayleigh
-// quotient of the start vector (a lower bound), one factorisation of
-// W - sigma I, sigma = rho0 (1 + 1e-4), certifies by its inertia that every
-// eigenvalue lies below sigma and gives one inverse-iteration step with
-// that shift; the Rayleigh quotient of the result is L (between rho0 and
-// sigma, and within ~theta^2 of lambda_max for the remaining angle theta).
-// Without a usable start, or when the certificate fails, the
-// tridiagonalisation and bisection above give L and one inverse-iteration
-// step gives the vector.  On return v holds the unit top eigenvector.
+// Solves (W - sigma I) x = r by Gaussian elimination without pivoting in
+// FP32, fully unrolled over the P columns: lane i keeps row i in registers
+// (R[c] = M[i][c]); at step k the pivot row is read from lane k and every
+// lane below subtracts its multiple.  A lane's row no longer changes once it
+// has been the pivot, so at the end lane i holds row i of the upper factor,
+// which the back substitution reads in place.  Returns the number of
+// negative pivots -- by Sylvester's law of inertia the number of
+// eigenvalues of W below sigma -- or -1 on a zero or non-finite pivot.
+// x: right-hand side in, solution out (lane-distributed).  FP32 suffices for
+// the count whenever sigma is separated from the spectrum by much more than
+// p eps32 ||W|| (the elimination of a definite matrix is backward stable);
+// x only needs to be a good direction, so the pivots are inverted with the
+// hardware reciprocal.
 template <int P>
-__device__ __forceinline__ double lambda_max_warm(const double (*W)[33], double (*M)[33], double* v,
-                                                  int p, const double* prev, double* wv,
-                                                  double* dg, double* eo, double* tv) {
-    float (*U)[33] = reinterpret_cast<float (*)[33]>(&M[0][0]);   // 33 x 33 floats fit
+__device__ __forceinline__ int shifted_solve(const double (&wr)[P], double sigma, double& x, int p) {
     const int lane = threadIdx.x & 63;
-    if (prev && prev[0] > 0.0) {
-        if (lane < p) v[lane] = prev[1 + lane];
-        __builtin_amdgcn_wave_barrier();
-        const double rho0 = rayleigh<P>(W, v, p);
+    float R[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) R[c] = lane < p ? (float)(wr[c] - (lane == c ? sigma : 0.0)) : 0.f;
+    float ri = lane < p ? (float)x : 0.f;
+    float inv_own = 0.f;   // lane k: 1 / pivot k
+    int neg = 0;
+    bool bad = false;
+    // static trip counts (full unroll, no register indexing); steps k >= p
+    // change nothing
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const bool kin = k < p;
+        const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(R[k]), k));
+        neg += kin && d < 0.f;
+        const bool good = d != 0.f && fabsf(d) < 1e37f;
+        bad = bad || (kin && !good);
+        const float inv = __builtin_amdgcn_rcpf(good ? d : 1.f);
+        if (lane == k) inv_own = kin ? inv : 0.f;
+        const float f = (kin && lane > k) ? R[k] * inv : 0.f;
+        ri = fmaf(-f, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ri), k)), ri);
+#pragma unroll
+        for (int c = k + 1; c < P; ++c)
+            R[c] = fmaf(-f, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(R[c]), k)), R[c]);
+    }
+    // back substitution: once x_k is known, every lane i < k removes U[i][k] x_k
+    float xi = 0.f;
+    float acc = ri;
+#pragma unroll
+    for (int k = P - 1; k >= 0; --k) {   // lanes k >= p hold acc = inv_own = 0
+        const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc * inv_own), k));
+        if (lane == k) xi = xk;
+        if (lane < k) acc = fmaf(-R[k], xk, acc);
+    }
+    x = lane < p ? (double)xi : 0.0;
+    return bad ? -1 : neg;
+}
+
+// lambda_max of the symmetric part of W (p x p floats in LDS) by one
+// wavefront, warm-started from the top eigenvector of the previous
+// subproblem of the same side (prev_L <= 0 means none; lane i < p holds its
+// component i in prev_v).  With rho0 the Rayleigh quotient of the start
+// vector (a lower bound), one factorisation of W - sigma I,
+// sigma = rho0 (1 + 1e-4), certifies by its inertia that every eigenvalue
+// lies below sigma and gives one inverse-iteration step with that shift; the
+// Rayleigh quotient of the result is L (between rho0 and sigma, and within
+// ~theta^2 of lambda_max for the remaining angle theta).  Without a usable
+// start, or when the certificate fails, the tridiagonalisation and
+// bisection above (on M, LDS) give L and one inverse-iteration step gives
+// the vector.  On return v (lane-distributed) is the unit top eigenvector.
+template <int P>
+__device__ __forceinline__ double lambda_max_warm(const float (*W)[33], double (*M)[33], int p,
+                                                  double prev_L, double prev_v, double& v,
+                                                  double* wv, double* dg, double* eo, double* tv) {
+    const int lane = threadIdx.x & 63;
+    double wr[P];
+    sym_row<P>(W, p, wr);
+    if (prev_L > 0.0) {
+        v = lane < p ? prev_v : 0.0;
+        const double rho0 = rayleigh<P>(wr, v);
         if (rho0 > 0.0 && rho0 < 1e300) {
-            const int cnt = shifted_solve<P>(W, rho0 * (1.0 + 1e-4), v, p, U);
-            normalise(v, p);
-            const double rho = rayleigh<P>(W, v, p);
+            const int cnt = shifted_solve<P>(wr, rho0 * (1.0 + 1e-4), v, p);
+            normalise(v);
+            const double rho = rayleigh<P>(wr, v);
             if (cnt == p && rho >= rho0 * (1.0 - 1e-12) && rho < 1e300) return rho;
         }
     }
-    for (int e = lane; e < p * p; e += 64) M[e / p][e % p] = W[e / p][e % p];
+    if (lane < p)
+#pragma unroll
+        for (int j = 0; j < P; ++j) M[lane][j] = wr[j];
     __builtin_amdgcn_wave_barrier();
     const double L = lambda_max_wave(M, p, tv, wv, dg, eo);
-    if (lane < p) v[lane] = 1.0;
-    __builtin_amdgcn_wave_barrier();
+    v = lane < p ? 1.0 : 0.0;
     if (L > 0.0 && L < 1e300) {
-        shifted_solve<P>(W, L * (1.0 + 1e-5), v, p, U);
-        normalise(v, p);
-    } else if (lane < p) {
-        v[lane] = 0.0;
+        shifted_solve<P>(wr, L * (1.0 + 1e-5), v, p);
+        normalise(v);
+    } else {
+        v = 0.0;
     }
     return L;
 }
@@ -312,10 +319,8 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     static_assert((size_t)NSLOT * 256 * 2 * (GROUPED ? GB : 1) <= kPgWords, "exchange words");
     __shared__ float sS[32][33];      // S (rows: M index, cols: p)
     __shared__ float sW[32][33];      // W (p x p)
-    __shared__ double sA[32][33];     // FP64 W for lambda_max
     __shared__ double sv[32], swv[32], sdg[32], seo[32];
     __shared__ double sM[32][33];     // work matrix of the eigenvalue solver
-    __shared__ double sev[32];        // top eigenvector
     __shared__ double s_red[4];
     __shared__ double s_pub[2][4][GB];    // grouped, by group parity: wave sums of own norms
     __shared__ double s_cons[2][4][GB];   //   wave sums of the polled norms
@@ -334,6 +339,13 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     __syncthreads();   // LDS of a previous subproblem on this workgroup
     Control* ctl = a.ctl;
     bool ok = true;
+    // warm start of lambda_max (wave 0), fetched now so the load is in
+    // flight during the exchange of S
+    double eig_L = 0.0, eig_v = 0.0;
+    if (a.kind == 0 && a.eig_in && wave == 0) {
+        eig_L = a.eig_in[0];
+        eig_v = lane < p ? a.eig_in[1 + lane] : 0.0;
+    }
 
     // ---------------- 1. small product S ------------------------------------
     const int Srows = (a.mode == 2) ? a.ell : p;
@@ -393,16 +405,12 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     double L = 1.0;
     if (a.kind == 0) {
         if (wave == 0) {
-            for (int e = lane; e < p * p; e += 64) {
-                const int i = e / p, j = e % p;
-                sA[i][j] = 0.5 * ((double)sW[i][j] + (double)sW[j][i]);
-            }
-            __builtin_amdgcn_wave_barrier();
-            const double lm = lambda_max_warm<16 * PT>(sA, sM, sev, p, a.eig_in, swv, sdg, seo, sv);
+            double ev;
+            const double lm = lambda_max_warm<16 * PT>(sW, sM, p, eig_L, eig_v, ev, swv, sdg, seo, sv);
             if (lane == 0) s_L = lm;
             if (a.eig_out && blk == 0) {
                 if (lane == 0) a.eig_out[0] = (lm > 0.0 && lm == lm) ? lm : 0.0;
-                if (lane < p) a.eig_out[1 + lane] = sev[lane];
+                if (lane < p) a.eig_out[1 + lane] = ev;
             }
         }
     }
@@ -455,6 +463,23 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 for (int i = 0; i < 4; ++i) bb[t][4 * hp + i] = acc[i];
             }
         }
+    }
+
+    // Q operand of the closing product (mode 2), fetched now so that its
+    // latency hides behind the inner loop (small tile counts only: registers)
+    constexpr bool QPRE = TILES <= 2;
+    float qpre[QPRE ? TILES : 1][4][2];
+    if constexpr (QPRE) {
+#pragma unroll
+        for (int t = 0; t < TILES; ++t)
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int hm = 0; hm < 2; ++hm) {
+                    const int64_t r = row_base + 16 * t + 4 * s + g4;
+                    const int k = 16 * hm + q16;
+                    qpre[t][s][hm] = (a.mode == 2 && a.part_out && r < a.rows && k < a.ell) ? a.Q[r * a.ell + k] : 0.f;
+                }
     }
 
     auto grad = [&](const float (&zz)[NR], const float (&b)[NR], float (&g)[NR]) {
@@ -621,6 +646,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             // a stop at step s is seen at most 2 GB - 1 steps later; the
             // iterates of the group under test are kept for the return value.
             static_assert(GB == 4, "four norms per exchange");
+            constexpr int POLL_AT = 1, TEST_AT = GB - 1;   // steps of the group after the publish
             const int glast = (kmax + GB - 1) / GB;
             const int gend = check ? glast + 1 : glast;
             const int q = quad_slot(lane);            // step of a group this lane reduces
@@ -747,8 +773,8 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                         continue;
                     }
                     if (u == 0 && gi >= 2) publish_group(gi - 1);
-                    if (u == 1 && testable(gi - 1)) poll_group(gi - 1);
-                    if (u == GB - 1 && testable(gi - 1)) {
+                    if (u == POLL_AT && testable(gi - 1)) poll_group(gi - 1);
+                    if (u == TEST_AT && testable(gi - 1)) {
                         const int gc = gi - 1;
                         double tot[GB];
                         if (!consume_group(gc, tot)) {
@@ -780,6 +806,15 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                             done = true;
                             break;
                         }
+                        if (gc == glast) {   // budget spent without a stop: Z_kmax
+#pragma unroll
+                            for (int t = 0; t < TILES; ++t)
+#pragma unroll
+                                for (int i = 0; i < NR; ++i) z[t][i] = sav[GB - 1][t][i];
+                            steps = kmax;
+                            done = true;
+                            break;
+                        }
                     }
                 }
                 if (!done) {
@@ -791,7 +826,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                             for (int i = 0; i < NR; ++i) sav[u][t][i] = cur[u][t][i];
                 }
             }
-            if (!done && ok) {   // budget spent without a stop: Z_kmax
+            if (!done && ok) {   // no group was testable: Z_kmax
 #pragma unroll
                 for (int t = 0; t < TILES; ++t)
 #pragma unroll
@@ -925,7 +960,8 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                     float av;
                     if (a.mode == 2) {
                         const int k = 16 * hm + q16;
-                        av = (r < a.rows && k < a.ell) ? a.Q[r * a.ell + k] : 0.f;
+                        if constexpr (QPRE) av = qpre[t < (QPRE ? TILES : 1) ? t : 0][s][hm];
+                        else av = (r < a.rows && k < a.ell) ? a.Q[r * a.ell + k] : 0.f;
                     } else {
                         av = (hm < PT) ? zt[wave][rr][16 * hm + q16] : 0.f;
                     }
