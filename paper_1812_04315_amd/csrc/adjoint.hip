@@ -586,14 +586,12 @@ int subproblem_adj(cnmf_tape* t, const Dev& d, int64_t rows, const float* Z0, in
     a.Ys = t->Ys;
     a.Vb = t->Vb;
     a.Lpart = t->Lpart;
-    // momentum weights of the forward kernel: step k uses (alpha_{k-2} - 1) / alpha_{k-1}
-    double alpha = 1.0;
-    a.beta[0] = 0.f;
-    a.beta[1] = 0.f;
-    for (int k = 2; k <= t->K; ++k) {
-        const double an = 0.5 * (1.0 + std::sqrt(4.0 * alpha * alpha + 1.0));
-        a.beta[k] = (float)((alpha - 1.0) / an);
-        alpha = an;
+    // momentum weights of the forward kernel (the same table): step k uses beta[k]
+    {
+        float tab[kMaxK + 1];
+        momentum_table(tab, t->K);
+        a.beta[0] = 0.f;
+        for (int k = 1; k <= t->K; ++k) a.beta[k] = tab[k - 1];
     }
     const unsigned blocks = nb(rows, kThreads);
     if (p <= 16) hipLaunchKernelGGL(k_nnls_adj<16>, dim3(blocks), dim3(kThreads), 0, d.stream, a);

@@ -82,6 +82,23 @@ int cnmf_create(cnmf_ctx** out, int device, void* stream) {
         delete c;
         return CNMF_EHIP;
     }
+    {
+        float* host = new (std::nothrow) float[kBetaLen];
+        bool good = host != nullptr && hipMalloc((void**)&c->beta, kBetaLen * sizeof(float)) == hipSuccess;
+        if (good) {
+            momentum_table(host, kBetaLen);
+            good = hipMemcpy(c->beta, host, kBetaLen * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+        }
+        delete[] host;
+        if (!good) {
+            (void)hipFree(c->ctl);
+            (void)hipFree(c->slots);
+            (void)hipFree(c->oxch);
+            if (c->beta) (void)hipFree(c->beta);
+            delete c;
+            return CNMF_ENOMEM;
+        }
+    }
     if (const char* e = std::getenv("CNMF_DLAG")) {
         const int v = std::atoi(e);
         if ((v >= 0 && v <= 4) || v == kGrouped) c->dlag = v;
@@ -98,6 +115,7 @@ int cnmf_destroy(cnmf_ctx* c) {
     if (c->ctl) (void)hipFree(c->ctl);
     if (c->slots) (void)hipFree(c->slots);
     if (c->oxch) (void)hipFree(c->oxch);
+    if (c->beta) (void)hipFree(c->beta);
     delete c;
     return CNMF_OK;
 }
@@ -248,6 +266,7 @@ int cnmf_nnls(cnmf_ctx* c, int64_t rows, int32_t p, float* Z, int64_t z_rs, int6
     a.Bgiven = B;
     a.slot_s = c->slots;
     a.slot_pg = c->slots + 1024;
+    a.beta = c->beta;
     a.ctl = c->ctl;
     a.tol_value = tol;
     a.inner_max = inner_max;
@@ -449,6 +468,7 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
     base.mode = comp ? 2 : 1;
     base.slot_s = c->slots;
     base.slot_pg = c->slots + 1024;
+    base.beta = c->beta;
     base.ctl = ctl;
     base.inner_max = prm->inner_max;
     base.inner_min = prm->inner_min;

@@ -128,6 +128,7 @@ void base_args(const cnmf_batch* b, int i, int tg, int tf, PhaseArgs* ga, PhaseA
     base.mode = 2;
     base.slot_s = b->xw[i];
     base.slot_pg = b->xw[i] + 1024;
+    base.beta = b->c->beta;
     base.ctl = b->c->ctl;
     base.inner_max = b->prm.inner_max;
     base.inner_min = b->prm.inner_min;

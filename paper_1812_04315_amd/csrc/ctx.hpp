@@ -16,6 +16,7 @@ struct cnmf_ctx {
     Control* ctl = nullptr;       // device
     uint64_t* slots = nullptr;    // device, tagged exchange words of the phase kernels
     uint64_t* oxch = nullptr;     // device, tagged exchange words of the orthonormalisation
+    float* beta = nullptr;        // device, momentum weights (kBetaLen)
     unsigned seq = 0;             // last tag used
     int dlag = -1;                // stop-test lag (-1: automatic, see the phase launcher)
     char* ws = nullptr;           // device workspace

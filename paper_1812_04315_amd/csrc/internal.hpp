@@ -108,11 +108,32 @@ __device__ __forceinline__ double wave_sum(double v) {
     return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
+// Pairwise sums across 16-lane rows (rows 0+1 and 2+3) and across the two
+// 32-lane halves, by the row and half swaps: both lanes of a pair add the
+// same two operands in the same order, so they hold the same bits.
+__device__ __forceinline__ double swap_add16(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    const double x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    const double y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+    return x + y;
+}
+__device__ __forceinline__ double swap_add32(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    const double x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    const double y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+    return x + y;
+}
+
 // Four wavefront sums at once: lane L returns the total over the wavefront of
 // v[quad_slot(L)].  Quad exchanges leave one partial of each of the four
-// values per quad, row rotations by 8 then 4 and lane exchanges across 16 and
-// 32 finish the sum; each step adds two operands that the partner lane adds in
-// the other order, so all lanes with the same slot hold the same bits.
+// values per quad, row rotations by 8 then 4 and the row and half swaps
+// finish the sum; each step adds two operands that the partner lane adds in
+// the same or the other order, so all lanes with the same slot hold the same
+// bits.
 __device__ __forceinline__ int quad_slot(int lane) { return 2 * (lane & 1) + ((lane >> 1) & 1); }
 __device__ __forceinline__ double wave_sum4(const double (&v)[4]) {
     const int lane = threadIdx.x & 63;
@@ -123,9 +144,7 @@ __device__ __forceinline__ double wave_sum4(const double (&v)[4]) {
     double b = (hi ? a1 : a0) + dpp_d<kDppXor2>(hi ? a0 : a1);
     b += dpp_d<kDppRor8>(b);
     b += dpp_d<kDppRor4>(b);
-    b += __shfl_xor(b, 16);
-    b += __shfl_xor(b, 32);
-    return b;
+    return swap_add32(swap_add16(b));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -315,6 +334,7 @@ struct PhaseArgs {
     float* part_out;         // [nblk][32][32] (may be null)
     uint64_t* slot_s;        // [1024] S exchange
     uint64_t* slot_pg;       // kPgWords projected-gradient exchange words
+    const float* beta;       // momentum weight of inner step K at beta[K - 1] (kBetaLen)
     unsigned seq;            // launch sequence (tag), 1 .. 2^22 - 1
     Control* ctl;
     // stopping
@@ -358,6 +378,22 @@ bool phase_grid(const Dev& d, int64_t rows, int* tiles, unsigned* nblk);
 hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles);
 constexpr int kPgSlots = 10;   // slots per workgroup for projected-gradient partials
 constexpr size_t kPgWords = 8192;   // projected-gradient exchange words
+// Momentum weights of the inner loop (Algorithm 2): alpha_0 = 1,
+// alpha_{k+1} = (1 + sqrt(4 alpha_k^2 + 1)) / 2, and inner step K uses
+// beta = (alpha_{K-2} - 1) / alpha_{K-1} (0 for K <= 2), rounded to FP32.  They
+// depend on K alone, so one table (host-made, FP64 recursion) serves every
+// launch; it covers the largest inner budget plus the steps a stop test lags.
+constexpr int kBetaLen = 100000 + 64;
+inline void momentum_table(float* out, int n) {
+    double alpha = 1.0;
+    float beta = 0.f;
+    for (int k = 0; k < n; ++k) {
+        out[k] = beta;
+        const double alpha_n = 0.5 * (1.0 + std::sqrt(std::fma(4.0 * alpha, alpha, 1.0)));
+        beta = (float)((alpha - 1.0) / alpha_n);
+        alpha = alpha_n;
+    }
+}
 constexpr size_t kSlotWords = 1024 + kPgWords;
 constexpr int kGrouped = 8;     // stop-test lag value selecting the grouped exchange
 constexpr int kEigWords = 33;   // {L, v[32]} per side and parity

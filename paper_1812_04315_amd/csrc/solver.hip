@@ -51,6 +51,12 @@ __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Moves an MFMA result into vector registers at this point of the program,
+// in the MFMA's own basic block, where the compiler spaces the reads from the
+// MFMA as the matrix core requires.  A read of the accumulator registers
+// placed right after a branch was seen to return a stale element.
+__device__ __forceinline__ void settle(v4f& acc) { asm volatile("" : "+v"(acc)); }
+
 __device__ __forceinline__ int perm16(int m) { return 4 * (m & 3) + (m >> 2); }
 
 __device__ __forceinline__ void slot_store(uint64_t* p, unsigned tag, uint32_t payload) {
@@ -171,15 +177,14 @@ __device__ __forceinline__ double lambda_max_wave(double (*A)[33], int p, double
 // owning row i of the symmetric part of W in FP64 registers (wr) and entry i
 // of vectors; everything else is lane reads (no LDS round trips).
 
-// wr = row `lane` of (W + W^T) / 2 for W (p x p floats, row stride 33);
+// wr = row `lane` of the symmetric W (FP64, LDS, 16-byte aligned rows);
 // zero outside p x p.
 template <int P>
-__device__ __forceinline__ void sym_row(const float (*W)[33], int p, double (&wr)[P]) {
+__device__ __forceinline__ void sym_row(const double (*W)[34], int p, double (&wr)[P]) {
     const int lane = threadIdx.x & 63;
     const int i = lane < P ? lane : 0;
 #pragma unroll
-    for (int j = 0; j < P; ++j)
-        wr[j] = (lane < p && j < p) ? 0.5 * ((double)W[i][j] + (double)W[j][i]) : 0.0;
+    for (int j = 0; j < P; ++j) wr[j] = (lane < p && j < p) ? W[i][j] : 0.0;
 }
 
 // v^T W v / v^T v on every lane (lane i < p holds v_i; zero elsewhere).
@@ -255,7 +260,7 @@ __device__ __forceinline__ int shifted_solve(const double (&wr)[P], double sigma
     return bad ? -1 : neg;
 }
 
-// lambda_max of the symmetric part of W (p x p floats in LDS) by one
+// lambda_max of the symmetric W (p x p, FP64 in LDS) by one
 // wavefront, warm-started from the top eigenvector of the previous
 // subproblem of the same side (prev_L <= 0 means none; lane i < p holds its
 // component i in prev_v).  With rho0 the Rayleigh quotient of the start
@@ -268,7 +273,7 @@ __device__ __forceinline__ int shifted_solve(const double (&wr)[P], double sigma
 // bisection above (on M, LDS) give L and one inverse-iteration step gives
 // the vector.  On return v (lane-distributed) is the unit top eigenvector.
 template <int P>
-__device__ __forceinline__ double lambda_max_warm(const float (*W)[33], double (*M)[33], int p,
+__device__ __forceinline__ double lambda_max_warm(const double (*W)[34], double (*M)[33], int p,
                                                   double prev_L, double prev_v, double& v,
                                                   double* wv, double* dg, double* eo, double* tv) {
     const int lane = threadIdx.x & 63;
@@ -319,12 +324,13 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     static_assert((size_t)NSLOT * 256 * 2 * (GROUPED ? GB : 1) <= kPgWords, "exchange words");
     __shared__ float sS[32][33];      // S (rows: M index, cols: p)
     __shared__ float sW[32][33];      // W (p x p)
+    __shared__ __align__(16) double sWd[32][34];   // (W + W^T) / 2 in FP64, for lambda_max
     __shared__ double sv[32], swv[32], sdg[32], seo[32];
     __shared__ double sM[32][33];     // work matrix of the eigenvalue solver
     __shared__ double s_red[4];
     __shared__ double s_pub[2][4][GB];    // grouped, by group parity: wave sums of own norms
     __shared__ double s_cons[2][4][GB];   //   wave sums of the polled norms
-    __shared__ int s_cok[2][4];           //   polled words all carried the group's tag
+    __shared__ __align__(16) int s_cok[2][4];   //   polled words all carried the group's tag
     __shared__ double s_tot;
     __shared__ double s_L;
     __shared__ int s_flag;
@@ -344,7 +350,8 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     double eig_L = 0.0, eig_v = 0.0;
     if (a.kind == 0 && a.eig_in && wave == 0) {
         eig_L = a.eig_in[0];
-        eig_v = lane < p ? a.eig_in[1 + lane] : 0.0;
+        const double e = a.eig_in[1 + (lane < p ? lane : p - 1)];
+        eig_v = lane < p ? e : 0.0;
     }
 
     // ---------------- 1. small product S ------------------------------------
@@ -356,7 +363,11 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     }
     __syncthreads();
     if (a.mode == 0) {
-        for (int e = threadIdx.x; e < p * p; e += kThreads) sW[e / p][e % p] = a.Wgiven[e];
+        for (int e = threadIdx.x; e < p * p; e += kThreads) {
+            const int i = e / p, j = e % p;
+            sW[i][j] = a.Wgiven[e];
+            sWd[i][j] = 0.5 * ((double)a.Wgiven[e] + (double)a.Wgiven[j * p + i]);
+        }
     } else if (a.kind != 2) {
         // this workgroup's share: entries e = blk + nblk * j, one wave each
         for (int e = (int)blk + (int)nblk * wave; e < nS; e += (int)nblk * 4) {
@@ -388,7 +399,11 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             }
         }
         if (a.mode == 1) {
-            for (int e = threadIdx.x; e < p * p; e += kThreads) sW[e / p][e % p] = sS[e / p][e % p];
+            for (int e = threadIdx.x; e < p * p; e += kThreads) {
+                const int i = e / p, j = e % p;
+                sW[i][j] = sS[i][j];
+                sWd[i][j] = 0.5 * ((double)sS[i][j] + (double)sS[j][i]);
+            }
         } else {
             // W = S^T S (l x p -> p x p), FP64 accumulation
             for (int e = threadIdx.x; e < p * p; e += kThreads) {
@@ -396,24 +411,15 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 double t = 0.0;
                 for (int k = 0; k < a.ell; ++k) t = fma((double)sS[k][i], (double)sS[k][j], t);
                 sW[i][j] = (float)t;
+                sWd[i][j] = (double)(float)t;   // symmetric: (i, j) and (j, i) sum alike
             }
         }
     }
     __syncthreads();
 
-    // ---------------- 2. Lipschitz constant (wave 0), B rows, Z rows --------
-    double L = 1.0;
-    if (a.kind == 0) {
-        if (wave == 0) {
-            double ev;
-            const double lm = lambda_max_warm<16 * PT>(sW, sM, p, eig_L, eig_v, ev, swv, sdg, seo, sv);
-            if (lane == 0) s_L = lm;
-            if (a.eig_out && blk == 0) {
-                if (lane == 0) a.eig_out[0] = (lm > 0.0 && lm == lm) ? lm : 0.0;
-                if (lane < p) a.eig_out[1 + lane] = ev;
-            }
-        }
-    }
+    // ---------------- 2. Z rows, B rows, Lipschitz constant (wave 0) --------
+    // The row loads are issued first so that they are in flight while wave 0
+    // finds lambda_max.
 
     // A operand of the gradient product: W[k][16h' + perm(m)] (Z W) or its
     // transpose (Z W^T), k = 16 h + 4 s + l / 16, m = l % 16.
@@ -431,38 +437,37 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
 
     const int64_t row_base = (int64_t)blk * (64 * TILES) + (int64_t)wave * (16 * TILES);
     float z[TILES][NR], bb[TILES][NR];
+    float dv[TILES][2][4];   // D[r][k], k = 16 hk + 4 s + l / 16 (mode 2)
+    // Loads are unconditional, from indexes clamped into the operands, and
+    // masked afterwards: no divergent branches, so they all issue back to back.
+    const int64_t rlast = a.rows > 0 ? a.rows - 1 : 0;
+    const bool has_rows = a.rows > 0;
 #pragma unroll
     for (int t = 0; t < TILES; ++t) {
         const int64_t r = row_base + 16 * t + q16;
         const bool act = r < a.rows;
+        const int64_t rc = act ? r : rlast;
 #pragma unroll
         for (int h = 0; h < PT; ++h)
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int c = 16 * h + 4 * s + g4;
+                const int cc = c < p ? c : p - 1;
                 const bool in = act && c < p;
-                z[t][4 * h + s] = in ? a.Z[r * a.z_rs + c * a.z_cs] : 0.f;
-                if (a.mode != 2) bb[t][4 * h + s] = in ? a.Bgiven[r * p + c] : 0.f;
+                const float zv = has_rows ? a.Z[rc * a.z_rs + cc * a.z_cs] : 0.f;
+                z[t][4 * h + s] = in ? zv : 0.f;
+                const float bv = (has_rows && a.mode != 2) ? a.Bgiven[rc * p + cc] : 0.f;
+                bb[t][4 * h + s] = in ? bv : 0.f;
             }
-        if (a.mode == 2) {
-            // B rows = D S: A operand S[k][16h' + perm(m)], B operand D[r][k]
 #pragma unroll
-            for (int hp = 0; hp < PT; ++hp) {
-                v4f acc = {0.f, 0.f, 0.f, 0.f};
+        for (int hk = 0; hk < 2; ++hk)
 #pragma unroll
-                for (int hk = 0; hk < 2; ++hk)
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const int k = 16 * hk + 4 * s + g4;
-                        const int c = 16 * hp + perm16(q16);
-                        const float av = (k < a.ell && c < p) ? sS[k][c] : 0.f;
-                        const float dv = (act && k < a.ell) ? a.D[r * a.d_rs + k * a.d_cs] : 0.f;
-                        acc = mfma16(av, dv, acc);
-                    }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) bb[t][4 * hp + i] = acc[i];
+            for (int s = 0; s < 4; ++s) {
+                const int k = 16 * hk + 4 * s + g4;
+                const int kc = k < a.ell ? k : a.ell - 1;
+                const float d = (has_rows && a.mode == 2) ? a.D[rc * a.d_rs + kc * a.d_cs] : 0.f;
+                dv[t][hk][s] = (act && k < a.ell) ? d : 0.f;
             }
-        }
     }
 
     // Q operand of the closing product (mode 2), fetched now so that its
@@ -478,8 +483,44 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 for (int hm = 0; hm < 2; ++hm) {
                     const int64_t r = row_base + 16 * t + 4 * s + g4;
                     const int k = 16 * hm + q16;
-                    qpre[t][s][hm] = (a.mode == 2 && a.part_out && r < a.rows && k < a.ell) ? a.Q[r * a.ell + k] : 0.f;
+                    const int64_t rc = r < a.rows ? r : rlast;
+                    const int kc = k < a.ell ? k : a.ell - 1;
+                    const float qv = (has_rows && a.mode == 2 && a.part_out) ? a.Q[rc * a.ell + kc] : 0.f;
+                    qpre[t][s][hm] = (r < a.rows && k < a.ell) ? qv : 0.f;
                 }
+    }
+
+    double L = 1.0;
+    if (a.kind == 0 && wave == 0) {
+        double ev;
+        const double lm = lambda_max_warm<16 * PT>(sWd, sM, p, eig_L, eig_v, ev, swv, sdg, seo, sv);
+        if (lane == 0) s_L = lm;
+        if (a.eig_out && blk == 0) {
+            if (lane == 0) a.eig_out[0] = (lm > 0.0 && lm == lm) ? lm : 0.0;
+            if (lane < p) a.eig_out[1 + lane] = ev;
+        }
+    }
+
+    if (a.mode == 2) {
+        // B rows = D S: A operand S[k][16h' + perm(m)], B operand D[r][k]
+#pragma unroll
+        for (int t = 0; t < TILES; ++t)
+#pragma unroll
+            for (int hp = 0; hp < PT; ++hp) {
+                v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int k = 16 * hk + 4 * s + g4;
+                        const int c = 16 * hp + perm16(q16);
+                        const float av = (k < a.ell && c < p) ? sS[k][c] : 0.f;
+                        acc = mfma16(av, dv[t][hk][s], acc);
+                    }
+                settle(acc);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) bb[t][4 * hp + i] = acc[i];
+            }
     }
 
     auto grad = [&](const float (&zz)[NR], const float (&b)[NR], float (&g)[NR]) {
@@ -490,6 +531,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             for (int h = 0; h < PT; ++h)
 #pragma unroll
                 for (int s = 0; s < 4; ++s) acc = mfma16(wA[hp][h][s], zz[4 * h + s], acc);
+            settle(acc);
 #pragma unroll
             for (int i = 0; i < 4; ++i) g[4 * hp + i] = acc[i];
         }
@@ -632,8 +674,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         for (int t = 0; t < TILES; ++t)
 #pragma unroll
             for (int i = 0; i < NR; ++i) gp[t][i] = g[t][i];
-        double alpha = 1.0;
-        float beta = 0.f;
+        float beta = 0.f;   // momentum weight of the next step (non-grouped loop)
         const bool check = forced < 0;
         int stop_at = -1;
         int K = 1;
@@ -642,15 +683,18 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             // Steps run in groups of GB: group gi holds steps GB (gi-1) + 1 .. GB gi.
             // The norm of step K - 1 is formed while the products of step K run.
             // A group's norms are published together at the first step of the
-            // next group, polled at its second step and tested at its last, so
-            // a stop at step s is seen at most 2 GB - 1 steps later; the
-            // iterates of the group under test are kept for the return value.
+            // next group; they are polled at the second step and tested at the
+            // last step of the GLAG-th group after theirs, so a stop at step s
+            // is seen at most (GLAG + 1) GB - 1 steps later; the iterates of the
+            // group under test are kept for the return value.
             static_assert(GB == 4, "four norms per exchange");
             constexpr int POLL_AT = 1, TEST_AT = GB - 1;   // steps of the group after the publish
+            constexpr int GLAG = 2;                          // groups between a group and its test
             const int glast = (kmax + GB - 1) / GB;
-            const int gend = check ? glast + 1 : glast;
+            const int gend = check ? glast + GLAG : glast;
             const int q = quad_slot(lane);            // step of a group this lane reduces
             float cur[GB][TILES][NR], sav[GB][TILES][NR], gb2[2][TILES][NR];
+            float sav2[GLAG > 1 ? GB : 1][TILES][NR];   // the group before sav (GLAG = 2)
             double pgv[GB];
             uint64_t pw[4][2];
 #pragma unroll
@@ -711,19 +755,18 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                     double r = (pj[0] + pj[1]) + (pj[2] + pj[3]);
                     r += dpp_d<kDppRor8>(r);
                     r += dpp_d<kDppRor4>(r);
-                    r += __shfl_xor(r, 16);
-                    r += __shfl_xor(r, 32);
+                    r = swap_add32(swap_add16(r));
                     const int wok = __all(okl);
                     if (lane < GB) s_cons[par][wave][q] = r;
                     if (lane == 0) s_cok[par][wave] = wok;
                     lds_barrier();
-                    if (s_cok[par][0] && s_cok[par][1] && s_cok[par][2] && s_cok[par][3]) {
+                    // flags and sums read together (one LDS round trip)
+                    const int4 f = *reinterpret_cast<const int4*>(&s_cok[par][0]);
 #pragma unroll
-                        for (int u = 0; u < GB; ++u)
-                            tot[u] = (s_cons[par][0][u] + s_cons[par][1][u]) +
-                                     (s_cons[par][2][u] + s_cons[par][3][u]);
-                        return true;
-                    }
+                    for (int u = 0; u < GB; ++u)
+                        tot[u] = (s_cons[par][0][u] + s_cons[par][1][u]) +
+                                 (s_cons[par][2][u] + s_cons[par][3][u]);
+                    if (f.x && f.y && f.z && f.w) return true;
                     if (spins >= (kSpinLimit >> 4)) return false;   // uniform: every wave counts alike
                     lds_barrier();   // every wave has read this round's partials
                     __builtin_amdgcn_s_sleep(1);
@@ -731,9 +774,17 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 }
             };
             bool done = false;
+            // momentum weights of the current group's steps; the next group's
+            // are fetched a group ahead
+            float bq[GB], bqn[GB];
+#pragma unroll
+            for (int u = 0; u < GB; ++u) bq[u] = a.beta[u];
             for (int gi = 1; gi <= gend && !done; ++gi) {
 #pragma unroll
+                for (int u = 0; u < GB; ++u) bqn[u] = a.beta[GB * gi + u];
+#pragma unroll
                 for (int u = 0; u < GB; ++u) {
+                    const float beta = bq[u];
                     K = GB * (gi - 1) + 1 + u;
                     // Z_{K-1}, Z_{K-2} and their gradients
                     float (&z1)[TILES][NR] = (u == 0) ? sav[GB - 1] : cur[(u + GB - 1) % GB];
@@ -757,9 +808,6 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                     pgv[(u + GB - 1) % GB] = pv;
 #pragma unroll
                     for (int t = 0; t < TILES; ++t) grad(cur[u][t], bb[t], g2[t]);
-                    const double alpha_n = 0.5 * (1.0 + sqrt(4.0 * alpha * alpha + 1.0));
-                    beta = (float)((alpha - 1.0) / alpha_n);
-                    alpha = alpha_n;
                     if (!check) {
                         if (K == kmax) {
 #pragma unroll
@@ -773,9 +821,14 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                         continue;
                     }
                     if (u == 0 && gi >= 2) publish_group(gi - 1);
-                    if (u == POLL_AT && testable(gi - 1)) poll_group(gi - 1);
-                    if (u == TEST_AT && testable(gi - 1)) {
-                        const int gc = gi - 1;
+                    if (u == POLL_AT && testable(gi - GLAG)) poll_group(gi - GLAG);
+                    if (u == TEST_AT && testable(gi - GLAG)) {
+                        const int gc = gi - GLAG;
+                        // iterates of the group under test
+                        auto tz = [&](int uu, int t, int i) -> float {
+                            if constexpr (GLAG > 1) return sav2[uu][t][i];
+                            else return sav[uu][t][i];
+                        };
                         double tot[GB];
                         if (!consume_group(gc, tot)) {
                             if (threadIdx.x == 0) raise_status(ctl, CNMF_ST_TIMEOUT);
@@ -801,7 +854,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
 #pragma unroll
                                     for (int t = 0; t < TILES; ++t)
 #pragma unroll
-                                        for (int i = 0; i < NR; ++i) z[t][i] = sav[uu][t][i];
+                                        for (int i = 0; i < NR; ++i) z[t][i] = tz(uu, t, i);
                             steps = (gc - 1) * GB + 1 + hit;
                             done = true;
                             break;
@@ -810,7 +863,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
 #pragma unroll
                             for (int t = 0; t < TILES; ++t)
 #pragma unroll
-                                for (int i = 0; i < NR; ++i) z[t][i] = sav[GB - 1][t][i];
+                                for (int i = 0; i < NR; ++i) z[t][i] = tz(GB - 1, t, i);
                             steps = kmax;
                             done = true;
                             break;
@@ -819,11 +872,16 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 }
                 if (!done) {
 #pragma unroll
+                    for (int u = 0; u < GB; ++u) bq[u] = bqn[u];
+#pragma unroll
                     for (int u = 0; u < GB; ++u)
 #pragma unroll
                         for (int t = 0; t < TILES; ++t)
 #pragma unroll
-                            for (int i = 0; i < NR; ++i) sav[u][t][i] = cur[u][t][i];
+                            for (int i = 0; i < NR; ++i) {
+                                if constexpr (GLAG > 1) sav2[u][t][i] = sav[u][t][i];
+                                sav[u][t][i] = cur[u][t][i];
+                            }
                 }
             }
             if (!done && ok) {   // no group was testable: Z_kmax
@@ -835,6 +893,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             }
         } else {
         kend = check ? kmax + DLAG : kmax;
+        float beta_n = a.beta[1];   // step K + 1, fetched a step ahead
         for (; K <= kend; ++K) {
             const int jst = K - DLAG;
             const bool test = check && jst >= a.inner_min && jst <= kmax;
@@ -853,9 +912,8 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                     }
                     grad(zn[t], bb[t], gn[t]);
                 }
-                const double alpha_n = 0.5 * (1.0 + sqrt(4.0 * alpha * alpha + 1.0));
-                beta = (float)((alpha - 1.0) / alpha_n);
-                alpha = alpha_n;
+                beta = beta_n;
+                beta_n = a.beta[K + 1];
 #pragma unroll
                 for (int j = NH - 1; j >= 1; --j)
 #pragma unroll
@@ -972,6 +1030,10 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             __syncthreads();
         }
         // reduce the 4 waves: element (M = 16 hm + 4 g4 + i, N = 16 hn + q16)
+#pragma unroll
+        for (int hm = 0; hm < MT; ++hm)
+#pragma unroll
+            for (int hn = 0; hn < PT; ++hn) settle(acc[hm][hn]);
 #pragma unroll
         for (int hm = 0; hm < MT; ++hm)
 #pragma unroll
