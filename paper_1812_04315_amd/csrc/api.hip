@@ -334,42 +334,43 @@ int rsi_run(cnmf_ctx* c, int64_t n, int64_t m, const float* X, const uint16_t* X
         if (bf) return sweep_left_bf16(d, n, m, Xb, ldx, l, B, l, Z, ldz, trans, pt);
         return sweep_left(d, n, m, X, ldx, l, B, l, Z, ldz, trans, pt);
     };
-    // orthonormal basis of Y (N x l) into Q, pool: Omega_R^T (n-space) or
-    // Omega_L (m-space); QT: optional transposed copy (l x ldt)
-    auto orth_n = [&](const float* Y, float* Q) -> hipError_t {
-        unsigned seq = 0;
-        hipError_t e = next_seq(c, &seq);
+    // orthonormal bases of an n-space panel Yn_ (n x l, pool Omega_R^T) and an
+    // m-space panel Ym_ (m x l, pool Omega_L) at once (independent panels);
+    // QmT: optional transposed copy (l x ldt)
+    uint64_t* xch2 = c->oxch + orth_exchange_words() / 2;
+    auto orth_nm = [&](const float* Yn_, float* Qn, const float* Ym_, float* Qm,
+                       float* QmT) -> hipError_t {
+        unsigned sa = 0, sb = 0;
+        hipError_t e = next_seq(c, &sa);
+        if (e == hipSuccess) e = next_seq(c, &sb);
         if (e != hipSuccess) return e;
-        return orth(d, n, l, Y, oRt, false, tau2, Q, nullptr, 0, nullptr, c->oxch, seq, c->ctl);
-    };
-    auto orth_m = [&](const float* Y, float* Q, float* QT) -> hipError_t {
-        unsigned seq = 0;
-        hipError_t e = next_seq(c, &seq);
-        if (e != hipSuccess) return e;
-        return orth(d, m, l, Y, oL, false, tau2, Q, QT, ldt, nullptr, c->oxch, seq, c->ctl);
+        const OrthArgs ga = orth_args(n, l, Yn_, oRt, false, tau2, Qn, nullptr, 0, nullptr, c->oxch,
+                                      sa, c->ctl, orth_pair_blocks(d, n));
+        const OrthArgs gb = orth_args(m, l, Ym_, oL, false, tau2, Qm, QmT, ldt, nullptr, xch2, sb,
+                                      c->ctl, orth_pair_blocks(d, m));
+        return orth_pair(d, ga, gb);
     };
 
     if (!bf && (prm->flags & CNMF_FLAG_VALIDATE_INPUT)) CK(check_input(d, n, m, X, ldx, c->ctl));
     CK(transpose(d, l, n, oR, n, oRt, l));                       // Omega_R^T, n x l
     CK(transpose(d, m, l, oL, l, oLT, ldt));                     // Omega_L^T, l x m
+    // The two chains (left and right bases) are independent: each pair of
+    // bases that both chains need at the same point is found in one launch.
     // Step 0: sketches X Omega_L and (Omega_R X)^T and their bases.
     CK(right(oLT, Yn));
-    CK(orth_n(Yn, QL));
     CK(left(oRt, Ym, false));
-    CK(orth_m(Ym, QRt, QRtT));
+    CK(orth_nm(Yn, QL, Ym, QRt, QRtT));
     for (int k = 1; k <= prm->q; ++k) {
-        // Q~_L^(k) = orth(X^T Q_L^(k-1)), kept in the Q_R output (m x l).
-        CK(left(QL, Ym, false));
-        CK(orth_m(Ym, QR_out, QLtT));
+        // Q~_L^(k) = orth(X^T Q_L^(k-1)), kept in the Q_R output (m x l), and
         // Q~_R^(k)^T = orth(X Q_R^(k-1)^T), kept in the Q_L output (n x l).
+        CK(left(QL, Ym, false));
         CK(right(QRtT, Yn));
-        CK(orth_n(Yn, QL_out));
+        CK(orth_nm(Yn, QL_out, Ym, QR_out, QLtT));
         // X Q~_L^(k) (n x l) and (Q~_R^(k) X)^T (m x l).
         CK(right(QLtT, XR_out));
         if (k < prm->q) {
             CK(left(QL_out, Ym, false));
-            CK(orth_n(XR_out, QL));
-            CK(orth_m(Ym, QRt, QRtT));
+            CK(orth_nm(XR_out, QL, Ym, QRt, QRtT));
         } else {
             CK(left(QL_out, XL_out, true));   // X_L = Q_L^T X, l x m
         }

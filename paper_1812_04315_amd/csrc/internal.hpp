@@ -272,7 +272,8 @@ hipError_t check_input(const Dev& d, int64_t R, int64_t C, const float* X, int64
                        Control* ctl);
 
 // orth.hip: CholeskyQR2 with the rank rule in one launch.  xch: exchange
-// words (orth_exchange_words()); seq: launch tag (< 2^22), fresh per call.
+// words (orth_exchange_words(), room for two panels at once; a single panel
+// uses the first half); seq: launch tag (< 2^22), fresh per call.
 // QT (optional): transposed copy of Q with row pitch ldqt.
 size_t orth_exchange_words();
 
@@ -310,6 +311,11 @@ hipError_t orth_batched(const Dev& d, const OrthArgs* args, const uint32_t* sche
 hipError_t orth(const Dev& d, int64_t N, int l, const float* Y, const float* pool,
                 bool pool_trans, double tau2, float* Q, float* QT, int64_t ldqt,
                 int32_t* replaced, uint64_t* xch, unsigned seq, Control* ctl);
+// Two independent panels in one launch (half of the workgroups each), so
+// their exchange latencies overlap; a and b come from orth_args() with xch
+// set to the two halves of the context's exchange words and fresh tags.
+hipError_t orth_pair(const Dev& d, OrthArgs a, OrthArgs b);
+unsigned orth_pair_blocks(const Dev& d, int64_t N);
 
 // small.hip
 hipError_t lipschitz(const Dev& d, int p, const float* W, double* out, Control* ctl);

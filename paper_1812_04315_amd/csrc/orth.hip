@@ -27,6 +27,8 @@
 // Gram itself.  No fences and no second launch are needed.
 #include "internal.hpp"
 
+#include <algorithm>
+
 namespace cnmf {
 
 namespace {
@@ -437,6 +439,12 @@ __global__ __launch_bounds__(kThreads) void k_orth(OrthArgs g) {
     orth_body(g, blockIdx.x, gridDim.x);
 }
 
+// Two panels: workgroups [0, a.nblk) factor a, the rest b.
+__global__ __launch_bounds__(kThreads) void k_orth2(OrthArgs a, OrthArgs b) {
+    if (blockIdx.x < a.nblk) orth_body(a, blockIdx.x, a.nblk);
+    else orth_body(b, blockIdx.x - a.nblk, b.nblk);
+}
+
 // Batched: workgroup s walks the rounds of sched (instance << 12 | block or
 // 0xffffffff); all blocks of a panel share a round and every workgroup is
 // resident (the same argument as for the batched subproblem kernel).
@@ -460,7 +468,7 @@ unsigned orth_blocks(const Dev& d, int64_t N) {
 
 }  // namespace
 
-size_t orth_exchange_words() { return (size_t)257 * kMaxPairs * 2; }
+size_t orth_exchange_words() { return (size_t)2 * 257 * kMaxPairs * 2; }
 
 size_t orth_batch_exchange_words(unsigned nblk) { return (size_t)(nblk + 1) * kMaxPairs * 2; }
 
@@ -497,6 +505,23 @@ hipError_t orth_batched(const Dev& d, const OrthArgs* args, const uint32_t* sche
     if (rounds < 1 || slots < 1) return hipSuccess;
     hipLaunchKernelGGL(k_orth_batched, dim3((unsigned)slots), dim3(kThreads), 0, d.stream, args,
                        sched, rounds);
+    return hipGetLastError();
+}
+
+unsigned orth_pair_blocks(const Dev& d, int64_t N) {
+    const unsigned half = (unsigned)std::max(1, d.num_cus / 2);
+    return std::min(orth_blocks(d, N), half);
+}
+
+hipError_t orth_pair(const Dev& d, OrthArgs a, OrthArgs b) {
+    if (a.N <= 0 || a.l <= 0 || b.N <= 0 || b.l <= 0) return hipErrorInvalidValue;
+    if (a.l > 32 || b.l > 32 || a.seq >= (1u << 22) || b.seq >= (1u << 22)) return hipErrorInvalidValue;
+    // every workgroup resident (one per compute unit at most): the panels'
+    // exchanges wait only on workgroups that are running
+    if (a.nblk < 1 || b.nblk < 1 || a.nblk > 256 || b.nblk > 256 ||
+        (int)(a.nblk + b.nblk) > d.num_cus)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_orth2, dim3(a.nblk + b.nblk), dim3(kThreads), 0, d.stream, a, b);
     return hipGetLastError();
 }
 
