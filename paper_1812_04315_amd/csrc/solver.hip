@@ -354,6 +354,65 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         eig_v = lane < p ? e : 0.0;
     }
 
+    // ---------------- 0. row loads ------------------------------------------
+    // Z rows, D rows and the Q operand do not depend on S: their loads are
+    // issued first, so they are in flight during the exchange of S and
+    // lambda_max.
+    const int64_t row_base = (int64_t)blk * (64 * TILES) + (int64_t)wave * (16 * TILES);
+    float z[TILES][NR], bb[TILES][NR];
+    float dv[TILES][2][4];   // D[r][k], k = 16 hk + 4 s + l / 16 (mode 2)
+    // Loads are unconditional, from indexes clamped into the operands, and
+    // masked afterwards: no divergent branches, so they all issue back to back.
+    const int64_t rlast = a.rows > 0 ? a.rows - 1 : 0;
+    const bool has_rows = a.rows > 0;
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+        const int64_t r = row_base + 16 * t + q16;
+        const bool act = r < a.rows;
+        const int64_t rc = act ? r : rlast;
+#pragma unroll
+        for (int h = 0; h < PT; ++h)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int c = 16 * h + 4 * s + g4;
+                const int cc = c < p ? c : p - 1;
+                const bool in = act && c < p;
+                const float zv = has_rows ? a.Z[rc * a.z_rs + cc * a.z_cs] : 0.f;
+                z[t][4 * h + s] = in ? zv : 0.f;
+                const float bv = (has_rows && a.mode != 2) ? a.Bgiven[rc * p + cc] : 0.f;
+                bb[t][4 * h + s] = in ? bv : 0.f;
+            }
+#pragma unroll
+        for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = 16 * hk + 4 * s + g4;
+                const int kc = k < a.ell ? k : a.ell - 1;
+                const float d = (has_rows && a.mode == 2) ? a.D[rc * a.d_rs + kc * a.d_cs] : 0.f;
+                dv[t][hk][s] = (act && k < a.ell) ? d : 0.f;
+            }
+    }
+
+    // Q operand of the closing product (mode 2), fetched now so that its
+    // latency hides behind the inner loop (small tile counts only: registers)
+    constexpr bool QPRE = TILES <= 2;
+    float qpre[QPRE ? TILES : 1][4][2];
+    if constexpr (QPRE) {
+#pragma unroll
+        for (int t = 0; t < TILES; ++t)
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int hm = 0; hm < 2; ++hm) {
+                    const int64_t r = row_base + 16 * t + 4 * s + g4;
+                    const int k = 16 * hm + q16;
+                    const int64_t rc = r < a.rows ? r : rlast;
+                    const int kc = k < a.ell ? k : a.ell - 1;
+                    const float qv = (has_rows && a.mode == 2 && a.part_out) ? a.Q[rc * a.ell + kc] : 0.f;
+                    qpre[t][s][hm] = (r < a.rows && k < a.ell) ? qv : 0.f;
+                }
+    }
+
     // ---------------- 1. small product S ------------------------------------
     const int Srows = (a.mode == 2) ? a.ell : p;
     const int nS = Srows * p;
@@ -417,9 +476,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     }
     __syncthreads();
 
-    // ---------------- 2. Z rows, B rows, Lipschitz constant (wave 0) --------
-    // The row loads are issued first so that they are in flight while wave 0
-    // finds lambda_max.
+    // ---------------- 2. B rows, Lipschitz constant (wave 0) ----------------
 
     // A operand of the gradient product: W[k][16h' + perm(m)] (Z W) or its
     // transpose (Z W^T), k = 16 h + 4 s + l / 16, m = l % 16.
@@ -434,61 +491,6 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 const int c = 16 * hp + perm16(q16);
                 wA[hp][h][s] = a.wt ? sW[c][k] : sW[k][c];
             }
-
-    const int64_t row_base = (int64_t)blk * (64 * TILES) + (int64_t)wave * (16 * TILES);
-    float z[TILES][NR], bb[TILES][NR];
-    float dv[TILES][2][4];   // D[r][k], k = 16 hk + 4 s + l / 16 (mode 2)
-    // Loads are unconditional, from indexes clamped into the operands, and
-    // masked afterwards: no divergent branches, so they all issue back to back.
-    const int64_t rlast = a.rows > 0 ? a.rows - 1 : 0;
-    const bool has_rows = a.rows > 0;
-#pragma unroll
-    for (int t = 0; t < TILES; ++t) {
-        const int64_t r = row_base + 16 * t + q16;
-        const bool act = r < a.rows;
-        const int64_t rc = act ? r : rlast;
-#pragma unroll
-        for (int h = 0; h < PT; ++h)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int c = 16 * h + 4 * s + g4;
-                const int cc = c < p ? c : p - 1;
-                const bool in = act && c < p;
-                const float zv = has_rows ? a.Z[rc * a.z_rs + cc * a.z_cs] : 0.f;
-                z[t][4 * h + s] = in ? zv : 0.f;
-                const float bv = (has_rows && a.mode != 2) ? a.Bgiven[rc * p + cc] : 0.f;
-                bb[t][4 * h + s] = in ? bv : 0.f;
-            }
-#pragma unroll
-        for (int hk = 0; hk < 2; ++hk)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = 16 * hk + 4 * s + g4;
-                const int kc = k < a.ell ? k : a.ell - 1;
-                const float d = (has_rows && a.mode == 2) ? a.D[rc * a.d_rs + kc * a.d_cs] : 0.f;
-                dv[t][hk][s] = (act && k < a.ell) ? d : 0.f;
-            }
-    }
-
-    // Q operand of the closing product (mode 2), fetched now so that its
-    // latency hides behind the inner loop (small tile counts only: registers)
-    constexpr bool QPRE = TILES <= 2;
-    float qpre[QPRE ? TILES : 1][4][2];
-    if constexpr (QPRE) {
-#pragma unroll
-        for (int t = 0; t < TILES; ++t)
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int hm = 0; hm < 2; ++hm) {
-                    const int64_t r = row_base + 16 * t + 4 * s + g4;
-                    const int k = 16 * hm + q16;
-                    const int64_t rc = r < a.rows ? r : rlast;
-                    const int kc = k < a.ell ? k : a.ell - 1;
-                    const float qv = (has_rows && a.mode == 2 && a.part_out) ? a.Q[rc * a.ell + kc] : 0.f;
-                    qpre[t][s][hm] = (r < a.rows && k < a.ell) ? qv : 0.f;
-                }
-    }
 
     double L = 1.0;
     if (a.kind == 0 && wave == 0) {
