@@ -40,6 +40,8 @@
 // its tag matches and needs no fence.  An FP64 value takes two words.
 #include "internal.hpp"
 
+#include <type_traits>
+
 namespace cnmf {
 
 namespace {
@@ -693,7 +695,6 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             constexpr int POLL_AT = 1, TEST_AT = GB - 1;   // steps of the group after the publish
             constexpr int GLAG = 2;                          // groups between a group and its test
             const int glast = (kmax + GB - 1) / GB;
-            const int gend = check ? glast + GLAG : glast;
             const int q = quad_slot(lane);            // step of a group this lane reduces
             float cur[GB][TILES][NR], sav[GB][TILES][NR], gb2[2][TILES][NR];
             float sav2[GLAG > 1 ? GB : 1][TILES][NR];   // the group before sav (GLAG = 2)
@@ -775,6 +776,11 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                     poll_group(gc);
                 }
             };
+            // The loop is instantiated twice, with and without the stopping
+            // test, so that neither carries the other's branches.
+            auto run_groups = [&](auto check_tag) {
+            constexpr bool CHECK = decltype(check_tag)::value;
+            const int gend = CHECK ? glast + GLAG : glast;
             bool done = false;
             // momentum weights of the current group's steps; the next group's
             // are fetched a group ahead
@@ -810,7 +816,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                     pgv[(u + GB - 1) % GB] = pv;
 #pragma unroll
                     for (int t = 0; t < TILES; ++t) grad(cur[u][t], bb[t], g2[t]);
-                    if (!check) {
+                    if constexpr (!CHECK) {
                         if (K == kmax) {
 #pragma unroll
                             for (int t = 0; t < TILES; ++t)
@@ -821,7 +827,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                             break;
                         }
                         continue;
-                    }
+                    } else {
                     if (u == 0 && gi >= 2) publish_group(gi - 1);
                     if (u == POLL_AT && testable(gi - GLAG)) poll_group(gi - GLAG);
                     if (u == TEST_AT && testable(gi - GLAG)) {
@@ -871,6 +877,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                             break;
                         }
                     }
+                    }   // CHECK
                 }
                 if (!done) {
 #pragma unroll
@@ -893,6 +900,9 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                     for (int i = 0; i < NR; ++i) z[t][i] = sav[GB - 1][t][i];
                 steps = kmax;
             }
+            };
+            if (check) run_groups(std::true_type{});
+            else run_groups(std::false_type{});
         } else {
         kend = check ? kmax + DLAG : kmax;
         float beta_n = a.beta[1];   // step K + 1, fetched a step ahead
