@@ -904,11 +904,14 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             if (check) run_groups(std::true_type{});
             else run_groups(std::false_type{});
         } else {
-        kend = check ? kmax + DLAG : kmax;
+        // instantiated with and without the stopping test (as above)
+        auto run_steps = [&](auto check_tag) {
+        constexpr bool CHECK = decltype(check_tag)::value;
+        kend = CHECK ? kmax + DLAG : kmax;
         float beta_n = a.beta[1];   // step K + 1, fetched a step ahead
         for (; K <= kend; ++K) {
             const int jst = K - DLAG;
-            const bool test = check && jst >= a.inner_min && jst <= kmax;
+            const bool test = CHECK && jst >= a.inner_min && jst <= kmax;
             // the poll of step K - DLAG is in flight during this step's compute
             if (test && wave == 0) poll_issue(jst, pwA);
             if (K <= kmax) {
@@ -940,7 +943,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                         gp[t][i] = g[t][i];
                         g[t][i] = gn[t][i];
                     }
-                if (check && K >= a.inner_min) {
+                if (CHECK && K >= a.inner_min) {
                     double v = 0.0;
 #pragma unroll
                     for (int t = 0; t < TILES; ++t) v += pg2_of(zh[0][t], g[t]);
@@ -969,6 +972,9 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         if (K > kend) K = kend;
         steps = stop_at >= 0 ? stop_at : kmax;
         out_idx = K - steps;   // 0 .. NH - 1
+        };
+        if (check) run_steps(std::true_type{});
+        else run_steps(std::false_type{});
         }
     }
 
