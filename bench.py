@@ -431,8 +431,10 @@ def bench_adjoint(args, torch, cnmf, synth):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md, not launched", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this library "
+              "has no multi-GPU path (rows of X would be split across GPUs, with an "
+              "all-reduce of the small Gram and partial products; not implemented)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
