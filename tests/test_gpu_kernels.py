@@ -170,6 +170,74 @@ def test_nnls_stopping_rule(rows, p, tol):
         assert rel_fro(host(Z), Zo) <= 1e-4
 
 
+def _oracle_pg_at(Z0, W, B, side, steps):
+    """Projected-gradient norm of the oracle's iterate after exactly `steps` steps."""
+    Zk, _, _ = oracle.nesterov_nnls(Z0, W, B, side, 0.0, steps, forced_steps=steps)
+    return oracle.pg_norm(Zk, W.astype(float), B.astype(float), side)
+
+
+@pytest.mark.parametrize("rows,p,frac,inner_max,inner_min", [
+    (300, 5, 0.9, 5000, 1),      # stops after the first step
+    (300, 5, 0.06, 5000, 1),     # stops inside the first group of four steps
+    (300, 5, 0.025, 5000, 1),    # at a group boundary
+    (300, 5, 0.01, 5000, 1),
+    (1, 1, 0.5, 50, 1),          # one variable: exact after one step
+    (2000, 15, 0.03, 5000, 1),
+    (2000, 15, 0.5, 5000, 6),    # the lower bound on the step count binds
+    (2000, 15, 1e-7, 5, 1),      # the step cap binds, not a multiple of four
+    (2000, 15, 1e-7, 3, 1),
+    (700, 12, 1e-7, 10, 1),
+    (700, 12, 0.0085, 5000, 1),
+    (700, 12, 0.2, 9, 9),        # lower bound equal to the cap
+    (4000, 20, 0.004, 5000, 3),
+    (257, 32, 0.0021, 5000, 2),
+])
+def test_nnls_stop_edges(rows, p, frac, inner_max, inner_min):
+    """Stopping rule near its edges (early stops, a binding lower bound or cap):
+    the step count equals the oracle's unless the oracle's norm at the
+    decisive step lies within 1e-3 of the tolerance, where one step either
+    way is allowed."""
+    say("nnls_stop_edges", rows, p, frac, inner_max, inner_min)
+    rng = np.random.default_rng(rows * 7 + p)
+    A = rng.random((3 * p, p))
+    W = (A.T @ A).astype(np.float32)
+    B = (rng.random((rows, 3 * p)) @ A).astype(np.float32)
+    Z0 = rng.random((rows, p)).astype(np.float32)
+    t = frac * oracle.pg_norm(Z0.astype(float), W.astype(float), B.astype(float), "G")
+    Z = dev(Z0)
+    steps, _, _ = cnmf.nnls(Z, dev(W), dev(B), t, inner_max, inner_min=inner_min)
+    Zo, ko, _ = oracle.nesterov_nnls(Z0, W, B, "G", t, inner_max, inner_min=inner_min)
+    k = int(host(steps)[0])
+    assert inner_min <= k <= inner_max or (k == ko == 0)
+    near = [j for j in (ko - 1, ko) if j >= max(inner_min, 1)
+            and abs(_oracle_pg_at(Z0, W, B, "G", j) - t) <= 1e-3 * t]
+    if near:
+        assert abs(k - ko) <= 1
+    else:
+        assert k == ko
+    if k == ko:
+        assert rel_fro(host(Z), Zo) <= 1e-4
+
+
+@pytest.mark.parametrize("m,p,frac,inner_min", [(150, 5, 0.5, 1), (3000, 15, 0.05, 4)])
+def test_nnls_stop_columns(m, p, frac, inner_min):
+    """Tolerance-driven stop on the F side (columns of a p x m factor)."""
+    say("nnls_stop_columns", m, p, frac, inner_min)
+    rng = np.random.default_rng(m + 3 * p)
+    A = rng.random((2 * p + 1, p))
+    W = (A.T @ A).astype(np.float32)
+    Bt = (rng.random((m, 2 * p + 1)) @ A).astype(np.float32)
+    F0 = rng.random((p, m)).astype(np.float32)
+    t = frac * oracle.pg_norm(F0.astype(float), W.astype(float), Bt.T.astype(float), "F")
+    F = dev(F0)
+    steps, _, _ = cnmf.nnls(F, dev(W), dev(Bt), t, 5000, inner_min=inner_min, by_columns=True)
+    Fo, ko, _ = oracle.nesterov_nnls(F0, W, Bt.T, "F", t, 5000, inner_min=inner_min)
+    k = int(host(steps)[0])
+    assert abs(k - ko) <= 1
+    if k == ko:
+        assert rel_fro(host(F), Fo) <= 1e-4
+
+
 def test_rre_matches_oracle():
     say("rre")
     rng = np.random.default_rng(9)
