@@ -844,17 +844,23 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                             done = true;
                             break;
                         }
-                        int hit = -1;
+                        // bit uu: step (gc - 1) GB + 1 + uu is testable and met the
+                        // bound (hm) or has a non-finite norm (nm); every lane
+                        // holds the same totals, so the masks are uniform
+                        int hm = 0, nm = 0;
 #pragma unroll
                         for (int uu = 0; uu < GB; ++uu) {
                             const int st = (gc - 1) * GB + 1 + uu;
-                            if (hit >= 0 || st < a.inner_min || st > kmax) continue;
-                            if (!(tot[uu] == tot[uu])) {
-                                if (blk == 0 && threadIdx.x == 0) raise_status(ctl, CNMF_ST_NONFINITE);
-                            } else if (tot[uu] <= tol2) {
-                                hit = uu;
-                            }
+                            const bool valid = st >= a.inner_min && st <= kmax;
+                            hm |= (valid && tot[uu] <= tol2) ? (1 << uu) : 0;
+                            nm |= (valid && !(tot[uu] == tot[uu])) ? (1 << uu) : 0;
                         }
+                        hm = __builtin_amdgcn_readfirstlane(hm);
+                        nm = __builtin_amdgcn_readfirstlane(nm);
+                        const int hit = hm ? __builtin_ctz((unsigned)hm) : -1;
+                        // non-finite norms at steps tested before the stop
+                        if ((hit >= 0 ? nm & ((1 << hit) - 1) : nm) && blk == 0 && threadIdx.x == 0)
+                            raise_status(ctl, CNMF_ST_NONFINITE);
                         if (hit >= 0) {
 #pragma unroll
                             for (int uu = 0; uu < GB; ++uu)
