@@ -41,6 +41,7 @@
 #include "internal.hpp"
 
 #include <type_traits>
+#include <utility>
 
 namespace cnmf {
 
@@ -177,7 +178,8 @@ __device__ __forceinline__ double lambda_max_wave(double (*A)[33], int p, double
 
 // The warm-started lambda_max below works on one wavefront with lane i < p
 // owning row i of the symmetric part of W in FP64 registers (wr) and entry i
-// of vectors; everything else is lane reads (no LDS round trips).
+// of vectors; everything else is lane reads or row broadcasts (no LDS round
+// trips).
 
 // wr = row `lane` of the symmetric W (FP64, LDS, 16-byte aligned rows);
 // zero outside p x p.
@@ -209,6 +211,62 @@ __device__ __forceinline__ void normalise(double& v) {
     v *= (nn > 0.0 && nn < 1e300) ? __builtin_amdgcn_rsq(nn) : 0.0;
 }
 
+// Lane k's value of v on every lane of its 16-lane row (DPP row_newbcast).
+template <int K>
+__device__ __forceinline__ float row_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + K, 0xf, 0xf, true));
+}
+template <class F, int... K>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, K...>) {
+    (f(std::integral_constant<int, K>{}), ...);
+}
+// f(integral_constant<int, k>) for k = 0 .. N - 1, in order
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
+// shifted_solve (below) for p <= 16: the rows live in lanes 0..15, one DPP
+// row, so the pivot row travels by row broadcasts instead of lane reads into
+// scalar registers; the counts are taken from lane 0, whose row holds the
+// system (lanes 16..63 run the same steps on zero rows).
+__device__ __forceinline__ int shifted_solve16(const double (&wr)[16], double sigma, double& x, int p) {
+    const int lane = threadIdx.x & 63;
+    float R[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) R[c] = lane < p ? (float)(wr[c] - (lane == c ? sigma : 0.0)) : 0.f;
+    float ri = lane < p ? (float)x : 0.f;
+    float inv_own = 0.f;
+    int neg = 0;
+    bool bad = false;
+    static_for<16>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const bool kin = k < p;
+        const float d = row_bcast<k>(R[k]);
+        neg += kin && d < 0.f;
+        const bool good = d != 0.f && fabsf(d) < 1e37f;
+        bad = bad || (kin && !good);
+        const float inv = __builtin_amdgcn_rcpf(good ? d : 1.f);
+        if (lane == k) inv_own = kin ? inv : 0.f;
+        const float f = (kin && lane > k) ? R[k] * inv : 0.f;
+        ri = fmaf(-f, row_bcast<k>(ri), ri);
+#pragma unroll
+        for (int c = k + 1; c < 16; ++c) R[c] = fmaf(-f, row_bcast<k>(R[c]), R[c]);
+    });
+    float xi = 0.f;
+    float acc = ri;
+    static_for<16>([&](auto kc) {
+        constexpr int k = 15 - decltype(kc)::value;
+        const float xk = row_bcast<k>(acc * inv_own);
+        if (lane == k) xi = xk;
+        if (lane < k) acc = fmaf(-R[k], xk, acc);
+    });
+    x = lane < p ? (double)xi : 0.0;
+    neg = __builtin_amdgcn_readfirstlane(neg);
+    bad = __builtin_amdgcn_readfirstlane((int)bad) != 0;
+    return bad ? -1 : neg;
+}
+
 // Solves (W - sigma I) x = r by Gaussian elimination without pivoting in
 // FP32, fully unrolled over the P columns: lane i keeps row i in registers
 // (R[c] = M[i][c]); at step k the pivot row is read from lane k and every
@@ -224,6 +282,9 @@ __device__ __forceinline__ void normalise(double& v) {
 // hardware reciprocal.
 template <int P>
 __device__ __forceinline__ int shifted_solve(const double (&wr)[P], double sigma, double& x, int p) {
+    if constexpr (P == 16) {
+        return shifted_solve16(wr, sigma, x, p);
+    } else {
     const int lane = threadIdx.x & 63;
     float R[P];
 #pragma unroll
@@ -260,6 +321,7 @@ __device__ __forceinline__ int shifted_solve(const double (&wr)[P], double sigma
     }
     x = lane < p ? (double)xi : 0.0;
     return bad ? -1 : neg;
+    }
 }
 
 // lambda_max of the symmetric W (p x p, FP64 in LDS) by one
