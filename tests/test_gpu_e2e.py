@@ -22,10 +22,10 @@ def _gpu_rsi(inst, q, ld=None):
 
 @pytest.mark.parametrize("seed", [0, 1])
 @pytest.mark.parametrize("ld", [None, 152])
-def test_rsi_config1(seed, ld):
+def test_rsi_small_instance(seed, ld):
     """200 x 150, rank 5, l = 15, q = 4: columns 6..15 of every panel are
     numerically absent and come from the other Gaussian draw on both sides."""
-    say("rsi_config1", seed, ld)
+    say("rsi_small_instance", seed, ld)
     inst = synth.instance(200, 150, 5, 10, seed=seed)
     _, (QL, QR, XL, XR) = _gpu_rsi(inst, 4, ld)
     ref = oracle.rsi(inst.X, inst.omega_L, inst.omega_R, 4)
@@ -74,9 +74,9 @@ def _solve_gpu(inst, X, comp, T, inner_max, stop_rule=cnmf.STOP_GLOBAL, replay=N
 
 @pytest.mark.parametrize("method", ["plain", "compressed"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_solve_config1(method, seed):
+def test_solve_small_instance(method, seed):
     """Config 1: 20 outer iterations x <= 10 inner steps, global bound."""
-    say("solve_config1", method, seed)
+    say("solve_small_instance", method, seed)
     inst = synth.instance(200, 150, 5, 10, seed=seed)
     X = dev(inst.X)
     comp = ref_comp = None

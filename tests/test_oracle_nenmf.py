@@ -45,7 +45,7 @@ def test_rre_bounded_below_by_svd_floor():
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_plain_rre_monotone_config1(seed):
+def test_plain_rre_monotone_small_instance(seed):
     inst = synth.instance(200, 150, 5, 10, seed=seed)
     res = oracle.nenmf(inst.X, inst.G0, inst.F0, 20, 10, keep_history=True)
     errs = [oracle.rre(inst.X, g, f) for g, f in res.history]
@@ -81,7 +81,7 @@ def test_replay_reproduces_counts():
     np.testing.assert_array_equal(a.G, b.G)
 
 
-def test_compressed_config1_reaches_low_error():
+def test_compressed_small_instance_reaches_low_error():
     inst = synth.instance(200, 150, 5, 10, seed=0)
     r = oracle.rsi(inst.X, inst.omega_L, inst.omega_R, 4)
     res = oracle.nenmf(inst.X, inst.G0, inst.F0, 300, 100, compressed=r, ratio=1e-6)
