@@ -285,42 +285,42 @@ __device__ __forceinline__ int shifted_solve(const double (&wr)[P], double sigma
     if constexpr (P == 16) {
         return shifted_solve16(wr, sigma, x, p);
     } else {
-    const int lane = threadIdx.x & 63;
-    float R[P];
+        const int lane = threadIdx.x & 63;
+        float R[P];
 #pragma unroll
-    for (int c = 0; c < P; ++c) R[c] = lane < p ? (float)(wr[c] - (lane == c ? sigma : 0.0)) : 0.f;
-    float ri = lane < p ? (float)x : 0.f;
-    float inv_own = 0.f;   // lane k: 1 / pivot k
-    int neg = 0;
-    bool bad = false;
-    // static trip counts (full unroll, no register indexing); steps k >= p
-    // change nothing
+        for (int c = 0; c < P; ++c) R[c] = lane < p ? (float)(wr[c] - (lane == c ? sigma : 0.0)) : 0.f;
+        float ri = lane < p ? (float)x : 0.f;
+        float inv_own = 0.f;   // lane k: 1 / pivot k
+        int neg = 0;
+        bool bad = false;
+        // static trip counts (full unroll, no register indexing); steps k >= p
+        // change nothing
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const bool kin = k < p;
-        const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(R[k]), k));
-        neg += kin && d < 0.f;
-        const bool good = d != 0.f && fabsf(d) < 1e37f;
-        bad = bad || (kin && !good);
-        const float inv = __builtin_amdgcn_rcpf(good ? d : 1.f);
-        if (lane == k) inv_own = kin ? inv : 0.f;
-        const float f = (kin && lane > k) ? R[k] * inv : 0.f;
-        ri = fmaf(-f, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ri), k)), ri);
+        for (int k = 0; k < P; ++k) {
+            const bool kin = k < p;
+            const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(R[k]), k));
+            neg += kin && d < 0.f;
+            const bool good = d != 0.f && fabsf(d) < 1e37f;
+            bad = bad || (kin && !good);
+            const float inv = __builtin_amdgcn_rcpf(good ? d : 1.f);
+            if (lane == k) inv_own = kin ? inv : 0.f;
+            const float f = (kin && lane > k) ? R[k] * inv : 0.f;
+            ri = fmaf(-f, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ri), k)), ri);
 #pragma unroll
-        for (int c = k + 1; c < P; ++c)
-            R[c] = fmaf(-f, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(R[c]), k)), R[c]);
-    }
-    // back substitution: once x_k is known, every lane i < k removes U[i][k] x_k
-    float xi = 0.f;
-    float acc = ri;
+            for (int c = k + 1; c < P; ++c)
+                R[c] = fmaf(-f, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(R[c]), k)), R[c]);
+        }
+        // back substitution: once x_k is known, every lane i < k removes U[i][k] x_k
+        float xi = 0.f;
+        float acc = ri;
 #pragma unroll
-    for (int k = P - 1; k >= 0; --k) {   // lanes k >= p hold acc = inv_own = 0
-        const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc * inv_own), k));
-        if (lane == k) xi = xk;
-        if (lane < k) acc = fmaf(-R[k], xk, acc);
-    }
-    x = lane < p ? (double)xi : 0.0;
-    return bad ? -1 : neg;
+        for (int k = P - 1; k >= 0; --k) {   // lanes k >= p hold acc = inv_own = 0
+            const float xk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc * inv_own), k));
+            if (lane == k) xi = xk;
+            if (lane < k) acc = fmaf(-R[k], xk, acc);
+        }
+        x = lane < p ? (double)xi : 0.0;
+        return bad ? -1 : neg;
     }
 }
 
