@@ -75,7 +75,7 @@ def _solve_gpu(inst, X, comp, T, inner_max, stop_rule=cnmf.STOP_GLOBAL, replay=N
 @pytest.mark.parametrize("method", ["plain", "compressed"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_solve_small_instance(method, seed):
-    """Config 1: 20 outer iterations x <= 10 inner steps, global bound."""
+    """The small instance: 20 outer iterations x <= 10 inner steps, global bound."""
     say("solve_small_instance", method, seed)
     inst = synth.instance(200, 150, 5, 10, seed=seed)
     X = dev(inst.X)
@@ -145,6 +145,23 @@ def test_ragged_shapes_compressed(n, m, p, nu):
     assert rel_fro(host(F), ref.F) <= PARITY_RTOL
     QL = host(comp[0])
     assert np.linalg.norm(QL.T @ QL - np.eye(p + nu)) <= 1e-5
+
+
+@pytest.mark.parametrize("p,nu", [(16, 8), (16, 16), (17, 6), (24, 8), (30, 2)])
+def test_wide_ranks_compressed(p, nu):
+    """Ranks at and past 16 (the 16-lane and the 32-lane forms of the warm
+    lambda_max certificate): iterates and every subproblem's L against the
+    oracle on shared compressed data and replayed step counts."""
+    say("wide_ranks", p, nu)
+    inst = synth.instance(300, 260, p, nu, seed=p + nu, snr_db=40.0)
+    ref_comp = oracle.rsi(inst.X, inst.omega_L, inst.omega_R, 2)
+    shared = tuple(dev(a) for a in (ref_comp.Q_L, ref_comp.Q_R, ref_comp.X_L, ref_comp.X_R))
+    shared32 = oracle.RSIResult(*(host(a) for a in shared))
+    ref = oracle.nenmf(inst.X, inst.G0, inst.F0, 8, 30, compressed=shared32)
+    G, F, tr = _solve_gpu(inst, None, shared, 8, 30, replay=ref.steps)
+    assert rel_fro(host(G), ref.G) <= PARITY_RTOL
+    assert rel_fro(host(F), ref.F) <= PARITY_RTOL
+    np.testing.assert_allclose(host(tr.lips), ref.lips, rtol=1e-4)
 
 
 def test_zero_outer_iterations_and_zero_factor():
