@@ -40,6 +40,9 @@ extern "C" {
 #define CNMF_ENOMEM     -2   /* workspace allocation failed                    */
 #define CNMF_EHIP       -3   /* a HIP runtime call failed                      */
 #define CNMF_EDEVICE    -4   /* cnmf_status(): the device status word is set   */
+#define CNMF_ENODERIV   -5   /* cnmf_adj_backward(): the rank rule replaced a
+                                basis column, where the bases of Algorithm 2
+                                have no derivative                            */
 
 /* ---- device status word bits (cnmf_status) ----------------------------- */
 #define CNMF_ST_NONFINITE   0x01  /* NaN/Inf met in data, a Gram or a norm     */
@@ -63,6 +66,17 @@ extern "C" {
 #define CNMF_METHOD_PLAIN       0  /* NeNMF on X (Sec. 2)                   */
 #define CNMF_METHOD_COMPRESSED  1  /* NeNMF on X_L, X_R (Algorithm 1)       */
 
+#define CNMF_SOLVER_NESTEROV  0  /* NeNMF inner loop (Sec. 2)                             */
+#define CNMF_SOLVER_HALS      1  /* HALS column sweeps (Sec. 1, Cichocki 2007), inner_max
+                                    sweeps per subproblem                                */
+#define CNMF_SOLVER_MU        2  /* multiplicative updates in the semi-NMF form of Ding
+                                    et al. 2010 (Sec. 3), inner_max per subproblem       */
+
+#define CNMF_RESTART_NONE      0
+#define CNMF_RESTART_GRADIENT  1  /* O'Donoghue and Candes 2015 (Sec. 4 footnote): the
+                                     momentum of a row restarts when its gradient at the
+                                     extrapolated point opposes the last step            */
+
 typedef struct cnmf_params {
     int32_t p;            /* factorisation rank, 1 <= p <= 32 (Eq. (1))                */
     int32_t nu;           /* oversampling: sketch width l = p + nu, l <= min(n,m), <= 32;
@@ -76,11 +90,17 @@ typedef struct cnmf_params {
     int32_t stop_rule;    /* CNMF_STOP_*                                                */
     int32_t sweep_prec;   /* CNMF_PREC_*: arithmetic of the X-sized sweeps              */
     int32_t flags;        /* CNMF_FLAG_*                                                */
+    int32_t solver;       /* CNMF_SOLVER_*: update rule of every subproblem             */
+    int32_t restart;      /* CNMF_RESTART_*: adaptive restart of the Nesterov momentum  */
     int32_t reserved;     /* must be 0                                                  */
+    double  time_budget;  /* > 0: device seconds after which the outer loop stops
+                             (Sec. 3 admits a time limit as the outer stopping
+                             criterion); 0: run all outer_iters                        */
 } cnmf_params;
 
 /* Fills p = 0 ... with the library defaults (q = 4, inner_max = 500,
- * inner_min = 1, inner_ratio = 1e-3, tau2 = 1e-9, global stop, FP32). */
+ * inner_min = 1, inner_ratio = 1e-3, tau2 = 1e-9, global stop, FP32,
+ * Nesterov inner loop without restart, no time budget). */
 void cnmf_params_default(cnmf_params* out);
 
 /* Optional per-outer-iteration trace of cnmf_solve.  Every pointer is a
@@ -93,6 +113,10 @@ typedef struct cnmf_trace {
                           at the end of every outer iteration                        */
     float*    G_hist;  /* T x n x p: G after every outer iteration                  */
     float*    F_hist;  /* T x p x m: F after every outer iteration                  */
+    float*    W_hist;  /* T x 2 x p x p: the Gram W each subproblem used (FP32, as
+                          in its gradient; L is computed from (W + W^T) / 2)        */
+    int32_t*  outer_done; /* 1: outer iterations completed (< T when the time
+                          budget ran out; later entries of the trace unset)        */
 } cnmf_trace;
 
 typedef struct cnmf_ctx cnmf_ctx;
@@ -143,6 +167,33 @@ int cnmf_rsi_bf16(cnmf_ctx* ctx, int64_t n, int64_t m, const uint16_t* Xb,
                   const float* omega_R, float* Q_L, float* Q_R, float* X_L,
                   float* X_R);
 
+/* Compression matrices of Sec. 3 (Algorithm 1 takes L, R as inputs), in the
+ * layout of cnmf_rsi's outputs (Q_L n x l with X_L = Q_L^T X, Q_R m x l with
+ * X_R = X Q_R; l = p + nu), for the compressed solve:
+ *   CNMF_COMPRESS_RSI       randomized subspace iteration, Algorithm 2
+ *                           (identical to cnmf_rsi);
+ *   CNMF_COMPRESS_GAUSSIAN  the plain random projection of Sec. 3: Gaussian
+ *                           matrices scaled by 1/sqrt(l), Q_L = Omega_R^T /
+ *                           sqrt(l), Q_R = Omega_L / sqrt(l) (not orthonormal;
+ *                           q and tau2 unused); one pass over X;
+ *   CNMF_COMPRESS_POWER     randomized power iteration without
+ *                           re-orthonormalisation (the structured random
+ *                           projection Sec. 3 cites): Q_R = orth((X^T X)^q
+ *                           Omega_L), Q_L = orth((X X^T)^q Omega_R^T), each
+ *                           intermediate product scaled to unit Frobenius norm
+ *                           (ranges unchanged), one CholeskyQR2 with the rank
+ *                           rule of cnmf_rsi at the end; the same 2q + 1
+ *                           passes over X per chain as Algorithm 2, in exact
+ *                           arithmetic the same subspaces, but the weak
+ *                           directions drown in FP32 rounding after the powers.
+ * Arguments as cnmf_rsi (FP32 sweeps). */
+#define CNMF_COMPRESS_RSI       0
+#define CNMF_COMPRESS_GAUSSIAN  1
+#define CNMF_COMPRESS_POWER     2
+int cnmf_compress(cnmf_ctx* ctx, int32_t kind, int64_t n, int64_t m, const float* X,
+                  int64_t ldx, const cnmf_params* prm, const float* omega_L,
+                  const float* omega_R, float* Q_L, float* Q_R, float* X_L, float* X_R);
+
 /* Round X (n x m, ldx) to bfloat16 (round to nearest even) into Xb (ldxb). */
 int cnmf_to_bf16(cnmf_ctx* ctx, int64_t n, int64_t m, const float* X,
                  int64_t ldx, uint16_t* Xb, int64_t ldxb);
@@ -154,8 +205,9 @@ int cnmf_to_bf16(cnmf_ctx* ctx, int64_t n, int64_t m, const float* X,
  *   replay optional device int32 T x 2: run exactly these inner step counts
  *          instead of testing the gradient bound (parity runs).
  * Per outer iteration: G update on Eq. (2) (or its compressed form), then F
- * update on Eq. (3), each by one Nesterov inner loop with step 1/L,
- * L = lambda_max(W) in FP64, projected gradient norms in FP64. */
+ * update on Eq. (3), each by one Nesterov inner loop with step 1/L, where L
+ * is an upper bound of lambda_max(W) within 1e-12 relative (FP64), and the
+ * projected gradient norms are summed in FP64. */
 int cnmf_solve(cnmf_ctx* ctx, int method, int64_t n, int64_t m,
                const float* X, int64_t ldx,
                const float* Q_L, const float* Q_R, const float* X_L,
@@ -282,8 +334,10 @@ int cnmf_batch_solve(cnmf_batch* b, int32_t use_graph);
  *   dL/dX (n x m, row pitch lddx) and, if non-NULL, dL/dG0, dL/dF0.  Each
  *   checkpoint segment is recomputed; the subproblems are reversed through
  *   their projections and momentum, L = lambda_max(W) through its top
- *   eigenvector, the bases through the thin-QR adjoint (no basis column may
- *   have been replaced by the rank rule).  The tape can be reused. */
+ *   eigenvector, the bases through the thin-QR adjoint.  Returns
+ *   CNMF_ENODERIV, computing nothing, when the rank rule replaced a basis
+ *   column during the forward pass (the bases have no derivative there).
+ *   The tape can be reused. */
 typedef struct cnmf_tape cnmf_tape;
 int cnmf_adj_forward(cnmf_ctx* ctx, int64_t n, int64_t m, const float* X, int64_t ldx,
                      const cnmf_params* prm, int32_t ckpt, const float* omega_L,

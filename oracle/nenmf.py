@@ -213,6 +213,53 @@ def rsi(X, omega_L, omega_R, q: int, tau2: float = 1e-9, bf16: bool = False) -> 
     return RSIResult(Q_L=Qt_Rt, Q_R=Qt_L, X_L=B.T.copy(), X_R=A, replaced=reps)
 
 
+def compress_gaussian(X, omega_L, omega_R) -> RSIResult:
+    """The plain random projection of Sec. 3 (Algorithm 1 with scaled
+    Gaussian compression matrices): L = Omega / sqrt(nu) for a nu x n
+    Gaussian Omega, and likewise R.  Here nu = l, L = Omega_R / sqrt(l)
+    (l x n, so Q_L = L^T is n x l), R = Omega_L / sqrt(l) (m x l), and the
+    compressed data are X_L = L X and X_R = X R.  Q_L, Q_R are not
+    orthonormal."""
+    X = np.asarray(X, dtype=F64)
+    oL = np.asarray(omega_L, dtype=F64)
+    oR = np.asarray(omega_R, dtype=F64)
+    ell = oL.shape[1]
+    R = oL / math.sqrt(ell)
+    Lt = oR.T / math.sqrt(ell)
+    return RSIResult(Q_L=Lt, Q_R=R, X_L=Lt.T @ X, X_R=X @ R)
+
+
+def compress_power(X, omega_L, omega_R, q: int, tau2: float = 1e-9) -> RSIResult:
+    """Randomized power iteration without re-orthonormalisation (the
+    structured random projection Sec. 3 cites, of which Algorithm 2 is the
+    stable variant): the same two chains as ``rsi`` with the same number of
+    products, but only the final panels are orthonormalised:
+        Q_R = orth((X^T X)^q Omega_L),   Q_L = orth((X X^T)^q Omega_R^T),
+    then X_R = X Q_R and X_L = Q_L^T X.  Every intermediate panel is divided
+    by its Frobenius norm, which leaves its range unchanged (in exact
+    arithmetic the bases span the same subspaces as those of ``rsi``).
+    The final orthonormalisation uses the rank rule of ``orth`` with the same
+    pools as ``rsi``."""
+    if q < 1:
+        raise ValueError("q >= 1 required")
+    X = np.asarray(X, dtype=F64)
+    oL = np.asarray(omega_L, dtype=F64)
+    oRt = np.asarray(omega_R, dtype=F64).T
+
+    def unit(Y):
+        return Y / np.linalg.norm(Y)
+
+    Ym = oL                      # m-space chain: (X^T X)^q Omega_L
+    Yn = oRt                     # n-space chain: (X X^T)^q Omega_R^T
+    for _ in range(q):
+        Ym = unit(X.T @ unit(X @ Ym))
+        Yn = unit(X @ unit(X.T @ Yn))
+    QR, rR = orth(Ym, oL, tau2)
+    QL, rL = orth(Yn, oRt, tau2)
+    return RSIResult(Q_L=QL, Q_R=QR, X_L=QL.T @ X, X_R=X @ QR,
+                     replaced=[("R", rR), ("L", rL)])
+
+
 # ---------------------------------------------------------------------------
 # NeNMF inner loop (Sec. 2)
 # ---------------------------------------------------------------------------
@@ -243,7 +290,8 @@ def pg_norm(Z, W, B, side: str) -> float:
 
 
 def nesterov_nnls(Z0, W, B, side: str, tol: float, inner_max: int,
-                  inner_min: int = 1, forced_steps: int | None = None):
+                  inner_min: int = 1, forced_steps: int | None = None,
+                  pg_trace: list | None = None, restart: bool = False):
     """One NeNMF inner loop (Sec. 2) for min_{Z >= 0} 0.5||X - G F||^2 in one factor.
 
     Y_0 = Z_0 (the outer iterate), alpha_0 = 1.  Step k: Z_k is one projected
@@ -253,6 +301,15 @@ def nesterov_nnls(Z0, W, B, side: str, tol: float, inner_max: int,
     gradient at Z_k has norm <= tol; return Z_k (the last feasible iterate).
     With ``forced_steps`` the loop runs exactly that many steps and ignores
     the tolerance.  L = 0 (W = 0) leaves Z_0 unchanged and reports 0 steps.
+    ``pg_trace`` (a list) receives the projected-gradient norm at every Z_k,
+    also in forced runs (a record of how close each stop decision was).
+
+    ``restart``: adaptive restart (O'Donoghue and Candes, suggested in the
+    footnote of Sec. 4 for the non-monotone compressed error).  The
+    subproblem separates into independent rows of G (columns of F), each
+    with its own alpha series; a row restarts (alpha back to 1, so its next
+    point is Z_k itself) when its gradient-mapping step Y_k - Z_k and its
+    last move Z_k - Z_{k-1} have a positive inner product.
 
     Returns (Z, steps, L).
     """
@@ -267,16 +324,89 @@ def nesterov_nnls(Z0, W, B, side: str, tol: float, inner_max: int,
     Zprev = Z0.copy()
     Z = Z0.copy()
     alpha = 1.0
+    # restart: one alpha per independent row (G) or column (F)
+    axis = 1 if side == "G" else 0
+    alphas = np.ones(Z0.shape[1 - axis], dtype=F64) if restart else None
     k = 0
     for k in range(1, kmax + 1):
         Z = np.maximum(Y - gradient(Y, W, B, side) / L, 0.0)
-        alpha_next = (1.0 + math.sqrt(4.0 * alpha * alpha + 1.0)) / 2.0
-        Y = Z + ((alpha - 1.0) / alpha_next) * (Z - Zprev)
+        if restart:
+            again = np.sum((Y - Z) * (Z - Zprev), axis=axis) > 0.0
+            alphas = np.where(again, 1.0, alphas)
+            nxt = (1.0 + np.sqrt(4.0 * alphas * alphas + 1.0)) / 2.0
+            w = (alphas - 1.0) / nxt
+            Y = Z + (w[:, None] if side == "G" else w[None, :]) * (Z - Zprev)
+            alphas = nxt
+        else:
+            alpha_next = (1.0 + math.sqrt(4.0 * alpha * alpha + 1.0)) / 2.0
+            Y = Z + ((alpha - 1.0) / alpha_next) * (Z - Zprev)
+            alpha = alpha_next
         Zprev = Z
-        alpha = alpha_next
-        if forced_steps is None and k >= inner_min and pg_norm(Z, W, B, side) <= tol:
-            break
+        if forced_steps is None or pg_trace is not None:
+            pg = pg_norm(Z, W, B, side)
+            if pg_trace is not None:
+                pg_trace.append(pg)
+            if forced_steps is None and k >= inner_min and pg <= tol:
+                break
     return Z, k, L
+
+
+def hals_update(Z0, W, B, side: str, sweeps: int):
+    """HALS (Sec. 1 lists it among the classical NMF solvers; the compressed
+    form is the randomized HALS that Sec. 1 cites): ``sweeps`` passes over
+    the p coordinates in order, each coordinate set to the exact minimiser
+    of the subproblem in it with the others fixed, then clipped at 0:
+        z_j <- max(0, z_j - grad_j(z) / W_jj)
+    for every row of G (every column of F), with the gradient of the current
+    point.  A coordinate with W_jj = 0 is left unchanged."""
+    Z = np.asarray(Z0, dtype=F64).copy()
+    W = np.asarray(W, dtype=F64)
+    B = np.asarray(B, dtype=F64)
+    p = W.shape[0]
+    for _ in range(sweeps):
+        for j in range(p):
+            if not W[j, j] > 0.0:
+                continue
+            if side == "G":
+                g = Z @ W[:, j] - B[:, j]
+                Z[:, j] = np.maximum(Z[:, j] - g / W[j, j], 0.0)
+            else:
+                g = W[j, :] @ Z - B[j, :]
+                Z[j, :] = np.maximum(Z[j, :] - g / W[j, j], 0.0)
+    return Z
+
+
+def mu_update(Z0, W, B, side: str, iters: int):
+    """Multiplicative updates for the subproblem when W and B may have
+    negative entries (the compressed data of Algorithm 1 are instances of
+    semi-NMF, Sec. 3, after Ding et al.): with A+ = max(A, 0) and
+    A- = max(-A, 0) entrywise,
+        Z <- Z * sqrt((B+ + Z W-) / (B- + Z W+))      (G side; F: W- Z, W+ Z),
+    ``iters`` times.  A zero denominator leaves that entry unchanged."""
+    Z = np.asarray(Z0, dtype=F64).copy()
+    W = np.asarray(W, dtype=F64)
+    B = np.asarray(B, dtype=F64)
+    Wp, Wn = np.maximum(W, 0.0), np.maximum(-W, 0.0)
+    Bp, Bn = np.maximum(B, 0.0), np.maximum(-B, 0.0)
+    for _ in range(iters):
+        if side == "G":
+            num, den = Bp + Z @ Wn, Bn + Z @ Wp
+        else:
+            num, den = Bp + Wn @ Z, Bn + Wp @ Z
+        ratio = np.divide(num, den, out=np.ones_like(num), where=den > 0.0)
+        Z = Z * np.sqrt(ratio)
+    return Z
+
+
+def subproblem_objective(Z, W, B, side: str) -> float:
+    """0.5 tr(Z^T Z W) - tr(B^T Z) (G) or 0.5 tr(Z^T W Z) - tr(B^T Z) (F):
+    ||X - G F||^2 / 2 in the free factor, up to a constant."""
+    Z = np.asarray(Z, dtype=F64)
+    W = np.asarray(W, dtype=F64)
+    B = np.asarray(B, dtype=F64)
+    if side == "G":
+        return float(0.5 * np.sum((Z @ W) * Z) - np.sum(B * Z))
+    return float(0.5 * np.sum((W @ Z) * Z) - np.sum(B * Z))
 
 
 # ---------------------------------------------------------------------------
@@ -314,12 +444,14 @@ class NeNMFResult:
     tols: np.ndarray         # T x 2 tolerances in force at each solve
     tol0: float
     history: list            # [(G_t, F_t)] after each outer iteration (if kept)
+    pg: list = field(default_factory=list)   # [t][side] norms at every inner step (if kept)
 
 
 def nenmf(X, G0, F0, outer_iters: int, inner_max: int, inner_min: int = 1,
           ratio: float = 1e-3, stop_rule: str = STOP_GLOBAL,
           compressed: RSIResult | None = None, replay=None,
-          keep_history: bool = False) -> NeNMFResult:
+          keep_history: bool = False, keep_pg: bool = False,
+          solver: str = "nesterov", restart: bool = False) -> NeNMFResult:
     """Plain NeNMF (Sec. 2) or, given RSI output, compressed NeNMF (Algorithm 1).
 
     Each outer iteration updates G (Eq. (2)) and then F (Eq. (3)) with one
@@ -333,7 +465,12 @@ def nenmf(X, G0, F0, outer_iters: int, inner_max: int, inner_min: int = 1,
         divided by 10 whenever its inner loop stops within ``inner_min``
         steps.
       * ``subproblem``: each inner loop uses ratio * ||P grad(Z_0)||_F.
-    ``replay`` (T x 2 ints) forces the inner step counts.
+    ``replay`` (T x 2 ints) forces the inner step counts; a negative entry
+    leaves that inner loop to the gradient bound.  ``keep_pg`` records the
+    projected-gradient norm at every inner step of every subproblem.
+    ``solver``: "nesterov" (Sec. 2), or "hals" / "mu", which take exactly
+    inner_max updates per subproblem (or the replayed count) and no bound.
+    ``restart``: adaptive restart of the Nesterov loops (see nesterov_nnls).
     """
     X = None if X is None else np.asarray(X, dtype=F64)
     G = np.asarray(G0, dtype=F64).copy()
@@ -370,28 +507,47 @@ def nenmf(X, G0, F0, outer_iters: int, inner_max: int, inner_min: int = 1,
     lips = np.zeros((outer_iters, 2), dtype=F64)
     tols = np.zeros((outer_iters, 2), dtype=F64)
     hist = []
+    pgs = []
+
+    def forced_at(t, side):
+        if replay is None or int(replay[t][side]) < 0:
+            return None
+        return int(replay[t][side])
+
+    if solver not in ("nesterov", "hals", "mu"):
+        raise ValueError(solver)
+
+    def update(Z, W, B, side, tol_, forced, trace):
+        if solver == "nesterov":
+            return nesterov_nnls(Z, W, B, side, tol_, inner_max, inner_min, forced, trace,
+                                 restart=restart)
+        k = inner_max if forced is None else forced
+        fn = hals_update if solver == "hals" else mu_update
+        return fn(Z, W, B, side, k), k, 0.0
+
     for t in range(outer_iters):
-        forced = None if replay is None else replay[t]
+        tr_g = [] if keep_pg else None
+        tr_f = [] if keep_pg else None
         W, B = gdata(F)
         tg = tol_g if stop_rule == STOP_GLOBAL else ratio * pg_norm(G, W, B, "G")
         tols[t, 0] = tg
-        G, kg, lg = nesterov_nnls(G, W, B, "G", tg, inner_max, inner_min,
-                                  None if forced is None else int(forced[0]))
-        if stop_rule == STOP_GLOBAL and 1 <= kg <= inner_min:
+        G, kg, lg = update(G, W, B, "G", tg, forced_at(t, 0), tr_g)
+        if stop_rule == STOP_GLOBAL and solver == "nesterov" and 1 <= kg <= inner_min:
             tol_g /= 10.0
         W, B = fdata(G)
         tf = tol_f if stop_rule == STOP_GLOBAL else ratio * pg_norm(F, W, B, "F")
         tols[t, 1] = tf
-        F, kf, lf = nesterov_nnls(F, W, B, "F", tf, inner_max, inner_min,
-                                  None if forced is None else int(forced[1]))
-        if stop_rule == STOP_GLOBAL and 1 <= kf <= inner_min:
+        F, kf, lf = update(F, W, B, "F", tf, forced_at(t, 1), tr_f)
+        if stop_rule == STOP_GLOBAL and solver == "nesterov" and 1 <= kf <= inner_min:
             tol_f /= 10.0
         steps[t] = (kg, kf)
         lips[t] = (lg, lf)
         if keep_history:
             hist.append((G.copy(), F.copy()))
+        if keep_pg:
+            pgs.append((tr_g, tr_f))
     return NeNMFResult(G=G, F=F, steps=steps, lips=lips, tols=tols, tol0=tol0,
-                       history=hist)
+                       history=hist, pg=pgs)
 
 
 # ---------------------------------------------------------------------------
@@ -403,6 +559,46 @@ def rre(X, G, F) -> float:
     X = np.asarray(X, dtype=F64)
     R = X - np.asarray(G, dtype=F64) @ np.asarray(F, dtype=F64)
     return float(np.linalg.norm(R) / np.linalg.norm(X))
+
+
+def rre_expanded(X, G, F, x_norm2: float | None = None) -> float:
+    """The same error from ||X||^2 - 2 <G^T X, F> + <G^T G, F F^T>, all in
+    FP64: one product G^T X instead of the n x m residual, for large X (the
+    expansion loses about eps64 ||X||^2 / ||X - G F||^2 relative, far below
+    FP32 resolution at any error level met here)."""
+    X = np.asarray(X)
+    G = np.asarray(G, dtype=F64)
+    F = np.asarray(F, dtype=F64)
+    if x_norm2 is None:
+        x_norm2 = float(np.einsum("ij,ij->", X, X, dtype=F64))
+    GtX = (X.T @ G).T if X.dtype == F64 else (np.asarray(X, dtype=F64).T @ G).T
+    cross = float(np.sum(GtX * F))
+    quad = float(np.sum((G.T @ G) * (F @ F.T)))
+    r2 = max(x_norm2 - 2.0 * cross + quad, 0.0)
+    return math.sqrt(r2 / x_norm2)
+
+
+def rre_history(X, history, chunk: int = 48) -> np.ndarray:
+    """rre_expanded for every (G_t, F_t) of a history, with the products
+    G_t^T X of up to ``chunk`` snapshots formed in one pass over X."""
+    X = np.asarray(X)
+    Xd = X if X.dtype == F64 else X.astype(F64)
+    x_norm2 = float(np.einsum("ij,ij->", Xd, Xd))
+    out = np.empty(len(history), dtype=F64)
+    for c0 in range(0, len(history), chunk):
+        part = history[c0:c0 + chunk]
+        Gs = np.concatenate([np.asarray(g, dtype=F64) for g, _ in part], axis=1)
+        XtG = Xd.T @ Gs                                  # m x (count p)
+        col = 0
+        for i, (g, f) in enumerate(part):
+            g = np.asarray(g, dtype=F64)
+            f = np.asarray(f, dtype=F64)
+            p = g.shape[1]
+            cross = float(np.sum(XtG[:, col:col + p].T * f))
+            col += p
+            quad = float(np.sum((g.T @ g) * (f @ f.T)))
+            out[c0 + i] = math.sqrt(max(x_norm2 - 2.0 * cross + quad, 0.0) / x_norm2)
+    return out
 
 
 def svd_floor(X, p: int) -> float:

@@ -19,16 +19,20 @@ from dataclasses import dataclass
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcnmf.so")
 
-OK, EINVAL, ENOMEM, EHIP, EDEVICE = 0, -1, -2, -3, -4
+OK, EINVAL, ENOMEM, EHIP, EDEVICE, ENODERIV = 0, -1, -2, -3, -4, -5
 ST_NONFINITE, ST_NEGATIVE, ST_BREAKDOWN, ST_ZERO_LIPS, ST_TIMEOUT = 1, 2, 4, 8, 16
 STOP_GLOBAL, STOP_SUBPROBLEM = 0, 1
 PREC_FP32, PREC_BF16 = 0, 1
 FLAG_VALIDATE_INPUT = 1
 METHOD_PLAIN, METHOD_COMPRESSED = 0, 1
+SOLVER_NESTEROV, SOLVER_HALS, SOLVER_MU = 0, 1, 2
+RESTART_NONE, RESTART_GRADIENT = 0, 1
+COMPRESS_RSI, COMPRESS_GAUSSIAN, COMPRESS_POWER = 0, 1, 2
 
 EXPORTED = [
     "cnmf_params_default", "cnmf_strerror", "cnmf_create", "cnmf_destroy",
     "cnmf_set_stream", "cnmf_clock_hz", "cnmf_status", "cnmf_rsi", "cnmf_rsi_bf16",
+    "cnmf_compress",
     "cnmf_to_bf16", "cnmf_solve", "cnmf_rre", "cnmf_sweep_right", "cnmf_sweep_left",
     "cnmf_sweep_right_bf16", "cnmf_sweep_left_bf16",
     "cnmf_orth", "cnmf_lipschitz", "cnmf_nnls",
@@ -52,7 +56,8 @@ class Params(ctypes.Structure):
         ("inner_min", ctypes.c_int32), ("inner_ratio", ctypes.c_double),
         ("tau2", ctypes.c_double), ("stop_rule", ctypes.c_int32),
         ("sweep_prec", ctypes.c_int32), ("flags", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("solver", ctypes.c_int32), ("restart", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("time_budget", ctypes.c_double),
     ]
 
 
@@ -70,7 +75,8 @@ class Instance(ctypes.Structure):
 class Trace(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_void_p), ("lips", ctypes.c_void_p),
                 ("tols", ctypes.c_void_p), ("ticks", ctypes.c_void_p),
-                ("G_hist", ctypes.c_void_p), ("F_hist", ctypes.c_void_p)]
+                ("G_hist", ctypes.c_void_p), ("F_hist", ctypes.c_void_p),
+                ("W_hist", ctypes.c_void_p), ("outer_done", ctypes.c_void_p)]
 
 
 _lib = None
@@ -96,6 +102,8 @@ def lib() -> ctypes.CDLL:
             "cnmf_rsi": (ctypes.c_int, [P, I64, I64, P, I64, ctypes.POINTER(Params), P, P, P, P, P, P]),
             "cnmf_rsi_bf16": (ctypes.c_int, [P, I64, I64, P, I64, ctypes.POINTER(Params), P, P, P, P, P, P]),
             "cnmf_to_bf16": (ctypes.c_int, [P, I64, I64, P, I64, P, I64]),
+            "cnmf_compress": (ctypes.c_int, [P, I32, I64, I64, P, I64, ctypes.POINTER(Params), P, P,
+                                             P, P, P, P]),
             "cnmf_solve": (ctypes.c_int, [P, ctypes.c_int, I64, I64, P, I64, P, P, P, P,
                                           ctypes.POINTER(Params), P, P, ctypes.POINTER(Trace), P]),
             "cnmf_rre": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, P, I64, I32, P]),
@@ -135,9 +143,11 @@ def strerror(code: int) -> str:
 
 def params(p: int, nu: int = 10, q: int = 4, outer_iters: int = 200, inner_max: int = 500,
            inner_min: int = 1, inner_ratio: float = 1e-3, tau2: float = 1e-9,
-           stop_rule: int = STOP_GLOBAL, sweep_prec: int = PREC_FP32, flags: int = 0) -> Params:
+           stop_rule: int = STOP_GLOBAL, sweep_prec: int = PREC_FP32, flags: int = 0,
+           solver: int = SOLVER_NESTEROV, restart: int = RESTART_NONE,
+           time_budget: float = 0.0) -> Params:
     return Params(p, nu, q, outer_iters, inner_max, inner_min, inner_ratio, tau2, stop_rule,
-                  sweep_prec, flags, 0)
+                  sweep_prec, flags, solver, restart, 0, time_budget)
 
 
 # ---------------------------------------------------------------------------
@@ -250,6 +260,28 @@ def rsi(X, omega_L, omega_R, p: int, nu: int, q: int = 4, tau2: float = 1e-9,
     return QL, QR, XL, XR
 
 
+def compress(X, omega_L, omega_R, p: int, nu: int, q: int = 4, kind: int = COMPRESS_RSI,
+             tau2: float = 1e-9, out=None):
+    """Compression matrices and compressed data of Sec. 3 (``kind``: RSI,
+    the scaled Gaussian projection, or power iteration without
+    re-orthonormalisation).  Returns (Q_L, Q_R, X_L, X_R) as ``rsi``."""
+    torch = _torch()
+    n, m = X.shape
+    ell = p + nu
+    _need(X, torch.float32, "X", ld_ok=True)
+    _need(omega_L, torch.float32, "omega_L", (m, ell))
+    _need(omega_R, torch.float32, "omega_R", (ell, n))
+    if out is None:
+        dev = X.device
+        out = (torch.empty(n, ell, device=dev), torch.empty(m, ell, device=dev),
+               torch.empty(ell, m, device=dev), torch.empty(n, ell, device=dev))
+    QL, QR, XL, XR = out
+    prm = params(p, nu, q, tau2=tau2)
+    _call("cnmf_compress", context().h, kind, n, m, _ptr(X), _ld(X), ctypes.byref(prm),
+          _ptr(omega_L), _ptr(omega_R), _ptr(QL), _ptr(QR), _ptr(XL), _ptr(XR))
+    return QL, QR, XL, XR
+
+
 def rsi_bf16(Xb, omega_L, omega_R, p: int, nu: int, q: int = 4, tau2: float = 1e-9, out=None):
     """Algorithm 2 with the X-sized sweeps in BF16.  Xb is an int16 tensor
     holding bfloat16 bit patterns (see ``to_bf16``)."""
@@ -290,9 +322,12 @@ class SolveTrace:
     ticks: object
     G_hist: object
     F_hist: object
+    W_hist: object = None
+    outer_done: object = None
 
 
-def make_trace(n: int, m: int, p: int, T: int, device, history: bool = True) -> SolveTrace:
+def make_trace(n: int, m: int, p: int, T: int, device, history: bool = True,
+               grams: bool = False) -> SolveTrace:
     torch = _torch()
     return SolveTrace(
         steps=torch.zeros(T, 2, dtype=torch.int32, device=device),
@@ -300,16 +335,19 @@ def make_trace(n: int, m: int, p: int, T: int, device, history: bool = True) -> 
         tols=torch.zeros(T, 2, dtype=torch.float64, device=device),
         ticks=torch.zeros(T + 1, dtype=torch.int64, device=device),
         G_hist=torch.empty(T, n, p, device=device) if history else None,
-        F_hist=torch.empty(T, p, m, device=device) if history else None)
+        F_hist=torch.empty(T, p, m, device=device) if history else None,
+        W_hist=torch.empty(T, 2, p, p, device=device) if grams else None,
+        outer_done=torch.zeros(1, dtype=torch.int32, device=device))
 
 
 def solve(G, F, *, X=None, compressed=None, p: int | None = None, nu: int = 10,
           outer_iters: int = 200, inner_max: int = 500, inner_min: int = 1,
           inner_ratio: float = 1e-3, stop_rule: int = STOP_GLOBAL, trace: SolveTrace | None = None,
-          replay=None):
+          replay=None, solver: int = SOLVER_NESTEROV, restart: int = RESTART_NONE,
+          time_budget: float = 0.0):
     """NeNMF outer loop in place on G (n x p) and F (p x m).  Plain when
     ``compressed`` is None (needs X), else ``compressed = (Q_L, Q_R, X_L, X_R)``
-    from ``rsi``."""
+    from ``rsi`` (or any other compression of the same shapes)."""
     torch = _torch()
     n, pp = G.shape
     p = pp if p is None else p
@@ -333,12 +371,15 @@ def solve(G, F, *, X=None, compressed=None, p: int | None = None, nu: int = 10,
         raise ValueError("plain NeNMF needs X")
     if replay is not None:
         _need(replay, torch.int32, "replay", (outer_iters, 2))
-    prm = params(p, nu, 1, outer_iters, inner_max, inner_min, inner_ratio, stop_rule=stop_rule)
+    prm = params(p, nu, 1, outer_iters, inner_max, inner_min, inner_ratio, stop_rule=stop_rule,
+                 solver=solver, restart=restart, time_budget=time_budget)
     tr = None
     if trace is not None:
         tr = Trace(*[ctypes.c_void_p(0 if t is None else t.data_ptr()) for t in
-                     (trace.steps, trace.lips, trace.tols, trace.ticks, trace.G_hist, trace.F_hist)])
-    _call("cnmf_solve", context().h, method, n, m, _ptr(X), _ld(X) if X is not None else m,
+                     (trace.steps, trace.lips, trace.tols, trace.ticks, trace.G_hist, trace.F_hist,
+                      trace.W_hist, trace.outer_done)])
+    _call("cnmf_solve", context().h, method, n, m,
+          _ptr(X), _ld(X) if X is not None else m,
           _ptr(QL), _ptr(QR), _ptr(XL), _ptr(XR), ctypes.byref(prm), _ptr(G), _ptr(F),
           ctypes.byref(tr) if tr is not None else None, _ptr(replay))
     return G, F

@@ -416,6 +416,7 @@ struct cnmf_tape {
     std::vector<float*> Gc, Fc;                 // (G, F) at t = 0, ck, 2 ck, ...
     float *Gh = nullptr, *Fh = nullptr;         // ck x n x p, ck x p x m
     int32_t* replay = nullptr;                  // T x 2, all K
+    int32_t* rep = nullptr;                     // 4q x 32 replaced-column flags of the RSI
     float* part = nullptr;                      // sweep partials
     // reverse work buffers
     float *Gb = nullptr, *Fb = nullptr, *Gb2 = nullptr, *Fb2 = nullptr;
@@ -496,15 +497,18 @@ int rsi_forward(cnmf_tape* t) {
     const int64_t n = t->n, m = t->m;
     const int l = t->l, q = t->q;
     const double tau2 = 1e-9;
+    int nrep = 0;   // every orthonormalisation records its replaced columns
     auto orth_n = [&](const float* Y, float* Q) -> hipError_t {
         unsigned seq = 0;
         HK(next_seq(c, &seq));
-        return orth(d, n, l, Y, t->oRt, false, tau2, Q, nullptr, 0, nullptr, c->oxch, seq, c->ctl);
+        return orth(d, n, l, Y, t->oRt, false, tau2, Q, nullptr, 0, t->rep + 32 * nrep++, c->oxch,
+                    seq, c->ctl);
     };
     auto orth_m = [&](const float* Y, float* Q, float* QT) -> hipError_t {
         unsigned seq = 0;
         HK(next_seq(c, &seq));
-        return orth(d, m, l, Y, t->oL, false, tau2, Q, QT, t->ldt, nullptr, c->oxch, seq, c->ctl);
+        return orth(d, m, l, Y, t->oL, false, tau2, Q, QT, t->ldt, t->rep + 32 * nrep++, c->oxch,
+                    seq, c->ctl);
     };
     auto right = [&](const float* AT, float* Y) {
         return sweep_right(d, n, m, t->X, t->ldx, l, AT, t->ldt, true, Y, l, t->part);
@@ -757,6 +761,7 @@ int cnmf_adj_forward(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t 
     take((size_t)ckpt * n * p);
     take((size_t)ckpt * p * m);
     const size_t o_rep = ar.take<int32_t>((size_t)2 * T);
+    const size_t o_flags = ar.take<int32_t>((size_t)4 * q * 32);
     const size_t pf = std::max(sweep_right_partial_floats(c->dev, n, m),
                                sweep_left_partial_floats(c->dev, n, m));
     take(pf + 1);                                                              // part
@@ -795,6 +800,7 @@ int cnmf_adj_forward(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t 
     t->Gh = F(i++);
     t->Fh = F(i++);
     t->replay = reinterpret_cast<int32_t*>(t->mem + o_rep);
+    t->rep = reinterpret_cast<int32_t*>(t->mem + o_flags);
     t->part = F(i++);
     if (i != base_work) { cnmf_tape_destroy(t); return CNMF_EINVAL; }
     t->Gb = F(i++); t->Fb = F(i++); t->Gb2 = F(i++); t->Fb2 = F(i++);
@@ -813,7 +819,8 @@ int cnmf_adj_forward(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t 
     const Dev& d = c->dev;
     const uint64_t kk = (uint64_t)(uint32_t)t->K;
     int rc = CNMF_OK;
-    if (fill_u64(d, reinterpret_cast<uint64_t*>(t->replay), T, kk | (kk << 32)) != hipSuccess)
+    if (fill_u64(d, reinterpret_cast<uint64_t*>(t->replay), T, kk | (kk << 32)) != hipSuccess ||
+        fill_u64(d, reinterpret_cast<uint64_t*>(t->rep), 2 * q * 32, 0) != hipSuccess)
         rc = CNMF_EHIP;
     if (!rc) rc = rsi_forward(t);
     // outer loop with checkpoints every ckpt iterations
@@ -846,6 +853,16 @@ int cnmf_adj_backward(cnmf_tape* t, const float* dG, const float* dF, float* dX,
     const Dev& d = c->dev;
     const int64_t n = t->n, m = t->m;
     const int p = t->p, l = t->l, T = t->T, ck = t->ck;
+    {   // the thin-QR adjoint is the derivative of Algorithm 2's bases only
+        // when the rank rule replaced no column (a replaced column is a
+        // discontinuity of the basis in X): refuse before any work
+        std::vector<int32_t> flags((size_t)4 * t->q * 32);
+        CK(hipMemcpyAsync(flags.data(), t->rep, flags.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, d.stream));
+        CK(hipStreamSynchronize(d.stream));
+        for (const int32_t f : flags)
+            if (f) return CNMF_ENODERIV;
+    }
     CK(copy2d(d, n, p, dG, p, t->Gb, p));
     CK(copy2d(d, p, m, dF, m, t->Fb, m));
     CK(fillf(d, (int64_t)n * l, 0.f, t->XRb));

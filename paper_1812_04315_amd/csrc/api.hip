@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -36,6 +37,7 @@ const char* cnmf_strerror(int code) {
         case CNMF_ENOMEM: return "out of device memory";
         case CNMF_EHIP: return "HIP runtime error";
         case CNMF_EDEVICE: return "device reported an error (see status word)";
+        case CNMF_ENODERIV: return "no derivative: the rank rule replaced a basis column";
         default: return "unknown error";
     }
 }
@@ -404,6 +406,117 @@ int cnmf_rsi_bf16(cnmf_ctx* c, int64_t n, int64_t m, const uint16_t* Xb, int64_t
     return rsi_run(c, n, m, nullptr, Xb, ldxb, prm, omega_L, omega_R, Q_L, Q_R, X_L, X_R);
 }
 
+}  // extern "C"
+
+namespace {
+
+// The two variants of the compression of Sec. 3 that Algorithm 2 improves
+// on: the scaled Gaussian projection and power iteration without
+// re-orthonormalisation (the same chains as rsi_run, orthonormalised once).
+int compress_variant(cnmf_ctx* c, int kind, int64_t n, int64_t m, const float* X, int64_t ldx,
+                     const cnmf_params* prm, const float* oL, const float* oR, float* QL_out,
+                     float* QR_out, float* XL_out, float* XR_out) {
+    const int l = prm->p + prm->nu;
+    const int64_t ldt = (m + 3) / 4 * 4;
+    const bool power = kind == CNMF_COMPRESS_POWER;
+    Arena a;
+    const size_t o_YmT = a.take<float>((size_t)l * ldt);
+    const size_t o_YmTb = a.take<float>(power ? (size_t)l * ldt : 1);
+    const size_t o_QRT = a.take<float>(power ? (size_t)l * ldt : 1);
+    const size_t o_YnA = a.take<float>(power ? (size_t)n * l : 1);
+    const size_t o_YnB = a.take<float>(power ? (size_t)n * l : 1);
+    const size_t o_Ym = a.take<float>(power ? (size_t)m * l : 1);
+    const size_t o_oRt = a.take<float>(power ? (size_t)n * l : 1);
+    const size_t o_nrm = a.take<double>(kNormBlocks);
+    const size_t o_part = a.take<float>(std::max(sweep_right_partial_floats(c->dev, n, m),
+                                                 sweep_left_partial_floats(c->dev, n, m)));
+    int rc = ensure_ws(c, a.off);
+    if (rc) return rc;
+    if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
+    const Dev& d = c->dev;
+    float* YmT = at<float>(c, o_YmT);
+    float* pt = at<float>(c, o_part);
+    double* nrm = at<double>(c, o_nrm);
+    auto right = [&](const float* AT, float* Y) {      // Y (n x l) = X A, A given as l x ldt
+        return sweep_right(d, n, m, X, ldx, l, AT, ldt, true, Y, l, pt);
+    };
+    // Z = X^T B, written m x l (ldz = l) or transposed l x m with pitch ldz
+    auto left = [&](const float* B, float* Z, bool trans, int64_t ldz) {
+        return sweep_left(d, n, m, X, ldx, l, B, l, Z, ldz, trans, pt);
+    };
+    if (prm->flags & CNMF_FLAG_VALIDATE_INPUT) CK(check_input(d, n, m, X, ldx, c->ctl));
+    if (!power) {
+        // L = Omega_R / sqrt(l) (l x n), R = Omega_L / sqrt(l) (m x l)
+        const float s = (float)(1.0 / std::sqrt((double)l));
+        CK(transpose(d, m, l, oL, l, YmT, ldt));                 // Omega_L^T
+        CK(scale2d(d, l, m, YmT, ldt, YmT, ldt, s));             // R^T
+        CK(scale2d(d, m, l, oL, l, QR_out, l, s));               // Q_R = R
+        CK(transpose(d, l, n, oR, n, QL_out, l));                // Omega_R^T
+        CK(scale2d(d, n, l, QL_out, l, QL_out, l, s));           // Q_L = L^T
+        CK(right(YmT, XR_out));                                  // X_R = X R
+        CK(left(QL_out, XL_out, true, m));                       // X_L = L X (l x m)
+        return CNMF_OK;
+    }
+    float* YmTb = at<float>(c, o_YmTb);
+    float* QRT = at<float>(c, o_QRT);
+    float* YnA = at<float>(c, o_YnA);
+    float* YnB = at<float>(c, o_YnB);
+    float* Ym = at<float>(c, o_Ym);
+    float* oRt = at<float>(c, o_oRt);
+    CK(transpose(d, m, l, oL, l, YmT, ldt));                     // Omega_L^T
+    CK(transpose(d, l, n, oR, n, oRt, l));                       // Omega_R^T
+    // chain A: (X^T X)^q Omega_L, kept transposed between products;
+    // chain B: (X X^T)^q Omega_R^T.  Each product is scaled to unit
+    // Frobenius norm (its range is unchanged).
+    for (int k = 1; k <= prm->q; ++k) {
+        CK(right(YmT, YnA));
+        CK(normalize2d(d, n, l, YnA, l, nrm));
+        if (k < prm->q) {
+            CK(left(YnA, YmT, true, ldt));
+            CK(normalize2d(d, l, m, YmT, ldt, nrm));
+        } else {
+            CK(left(YnA, Ym, false, l));
+            CK(normalize2d(d, m, l, Ym, l, nrm));
+        }
+        CK(left(k == 1 ? oRt : YnB, YmTb, true, ldt));
+        CK(normalize2d(d, l, m, YmTb, ldt, nrm));
+        CK(right(YmTb, YnB));
+        CK(normalize2d(d, n, l, YnB, l, nrm));
+    }
+    unsigned sa = 0, sb = 0;
+    CK(next_seq(c, &sa));
+    CK(next_seq(c, &sb));
+    const OrthArgs ga = orth_args(n, l, YnB, oRt, false, prm->tau2, QL_out, nullptr, 0, nullptr,
+                                  c->oxch, sa, c->ctl, orth_pair_blocks(d, n));
+    const OrthArgs gb = orth_args(m, l, Ym, oL, false, prm->tau2, QR_out, QRT, ldt, nullptr,
+                                  c->oxch + orth_exchange_words() / 2, sb, c->ctl,
+                                  orth_pair_blocks(d, m));
+    CK(orth_pair(d, ga, gb));
+    CK(right(QRT, XR_out));                                      // X_R = X Q_R
+    CK(left(QL_out, XL_out, true, m));                           // X_L = Q_L^T X
+    return CNMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cnmf_compress(cnmf_ctx* c, int32_t kind, int64_t n, int64_t m, const float* X, int64_t ldx,
+                  const cnmf_params* prm, const float* omega_L, const float* omega_R, float* Q_L,
+                  float* Q_R, float* X_L, float* X_R) {
+    if (!c || n < 1 || m < 1) return CNMF_EINVAL;
+    if (kind != CNMF_COMPRESS_RSI && kind != CNMF_COMPRESS_GAUSSIAN && kind != CNMF_COMPRESS_POWER)
+        return CNMF_EINVAL;
+    int rc = check_params(prm, n, m, true);
+    if (rc) return rc;
+    if (prm->sweep_prec != CNMF_PREC_FP32) return CNMF_EINVAL;
+    if (bad_ptr(X) || ldx < m || bad_ptr(omega_L) || bad_ptr(omega_R)) return CNMF_EINVAL;
+    if (bad_ptr(Q_L) || bad_ptr(Q_R) || bad_ptr(X_L) || bad_ptr(X_R)) return CNMF_EINVAL;
+    if (kind == CNMF_COMPRESS_RSI)
+        return rsi_run(c, n, m, X, nullptr, ldx, prm, omega_L, omega_R, Q_L, Q_R, X_L, X_R);
+    return compress_variant(c, kind, n, m, X, ldx, prm, omega_L, omega_R, Q_L, Q_R, X_L, X_R);
+}
+
 int cnmf_to_bf16(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t ldx, uint16_t* Xb,
                  int64_t ldxb) {
     if (!c || n < 0 || m < 0 || bad_ptr(X) || bad_ptr(Xb) || ldx < m || ldxb < m)
@@ -416,10 +529,16 @@ int cnmf_to_bf16(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t ldx,
 // NeNMF outer loop, plain (Sec. 2) and compressed (Algorithm 1)
 // ---------------------------------------------------------------------------
 
-int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, int64_t ldx,
-               const float* Q_L, const float* Q_R, const float* X_L, const float* X_R,
-               const cnmf_params* prm, float* G, float* F, const cnmf_trace* trace,
-               const int32_t* replay) {
+}  // extern "C"
+
+namespace {
+
+// The outer loop of cnmf_solve.  ws: workspace base of at least `cap`
+// bytes, or null for the context's (growing) workspace.
+int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t m,
+              const float* X, int64_t ldx, const float* Q_L, const float* Q_R,
+              const float* X_L, const float* X_R, const cnmf_params* prm, float* G, float* F,
+              const cnmf_trace* trace, const int32_t* replay) {
     if (!c || n < 1 || m < 1) return CNMF_EINVAL;
     const bool comp = method == CNMF_METHOD_COMPRESSED;
     if (!comp && method != CNMF_METHOD_PLAIN) return CNMF_EINVAL;
@@ -449,16 +568,21 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
     const size_t o_sw = ar.take<float>(comp ? 1 : std::max(sweep_right_partial_floats(c->dev, n, m),
                                                             sweep_left_partial_floats(c->dev, n, m)));
     const size_t o_eig = ar.take<double>(4 * kEigWords);   // {L, v} per side and parity
-    rc = ensure_ws(c, ar.off);
-    if (rc) return rc;
+    if (ws) {
+        if (ar.off > cap) return CNMF_EINVAL;
+    } else {
+        rc = ensure_ws(c, ar.off);
+        if (rc) return rc;
+        ws = c->ws;
+    }
     if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
     const Dev& d = c->dev;
-    float* pG = at<float>(c, o_pG);
-    float* pF = at<float>(c, o_pF);
-    float* BG = at<float>(c, o_BG);
-    float* BF = at<float>(c, o_BF);
-    float* sw = at<float>(c, o_sw);
-    double* eig = at<double>(c, o_eig);
+    float* pG = reinterpret_cast<float*>(ws + o_pG);
+    float* pF = reinterpret_cast<float*>(ws + o_pF);
+    float* BG = reinterpret_cast<float*>(ws + o_BG);
+    float* BF = reinterpret_cast<float*>(ws + o_BF);
+    float* sw = reinterpret_cast<float*>(ws + o_sw);
+    double* eig = reinterpret_cast<double*>(ws + o_eig);
     auto eig_at = [&](int side, int par) { return eig + (size_t)(2 * side + par) * kEigWords; };
     Control* ctl = c->ctl;
     const bool global = prm->stop_rule == CNMF_STOP_GLOBAL;
@@ -475,6 +599,10 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
     base.inner_min = prm->inner_min;
     base.forced = -1;
     base.dlag = c->dlag;
+    base.solver = prm->solver == CNMF_SOLVER_HALS ? kSolverHals
+                : prm->solver == CNMF_SOLVER_MU   ? kSolverMu
+                : prm->restart == CNMF_RESTART_GRADIENT ? kSolverRestart
+                                                        : kSolverNesterov;
     // G update (Eq. (2) / Algorithm 1 with X_R, F_R): rows of G
     PhaseArgs ga = base;
     ga.rows = n;
@@ -519,6 +647,12 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
     };
 
     if (tr.ticks) CK(write_tick(d, (unsigned long long*)tr.ticks));
+    const bool budget = prm->time_budget > 0.0;
+    if (budget) {
+        const double ticks = prm->time_budget * c->clock_hz;
+        CK(arm_deadline(d, ctl, ticks < 1.8e19 ? (unsigned long long)ticks : ~0ull >> 1));
+    }
+    if (tr.outer_done) CK(fill_i32(d, tr.outer_done, 1, 0));
     {   // partial product of F0 for the first G update
         PhaseArgs a = fa;
         a.kind = 2;
@@ -555,6 +689,8 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
         if (tr.G_hist) a.hist = tr.G_hist + (size_t)t * n * p;
         a.eig_in = eig_at(0, (t + 1) & 1);
         a.eig_out = eig_at(0, t & 1);
+        if (tr.W_hist) a.w_out = tr.W_hist + (size_t)(2 * t) * p * p;
+        if (budget) a.stop_flag = &ctl->stop;
         CK(run(a, true));
         CK(bf());
         a = fa;
@@ -568,9 +704,30 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
         if (tr.ticks) a.tick_out = (unsigned long long*)(tr.ticks + 1 + t);
         a.eig_in = eig_at(1, (t + 1) & 1);
         a.eig_out = eig_at(1, t & 1);
+        if (tr.W_hist) a.w_out = tr.W_hist + (size_t)(2 * t + 1) * p * p;
+        if (tr.outer_done) {
+            a.done_out = tr.outer_done;
+            a.done_value = t + 1;
+        }
+        if (budget) {
+            a.stop_flag = &ctl->stop;
+            a.deadline = &ctl->deadline;
+        }
         CK(run(a, false));
     }
     return CNMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, int64_t ldx,
+               const float* Q_L, const float* Q_R, const float* X_L, const float* X_R,
+               const cnmf_params* prm, float* G, float* F, const cnmf_trace* trace,
+               const int32_t* replay) {
+    return solve_run(c, nullptr, 0, method, n, m, X, ldx, Q_L, Q_R, X_L, X_R, prm, G, F, trace,
+                     replay);
 }
 
 int cnmf_rre(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t ldx, int32_t p,

@@ -447,6 +447,11 @@ int cnmf_batch_create(cnmf_ctx* c, const cnmf_instance* inst, int32_t count,
                       cnmf_batch** out) {
     if (!c || !inst || !out || count < 1 || count >= (1 << 20)) return CNMF_EINVAL;
     *out = nullptr;
+    // the batched form runs the Nesterov inner loop without restart and
+    // without a time budget
+    if (!prm || prm->solver != CNMF_SOLVER_NESTEROV || prm->restart != CNMF_RESTART_NONE ||
+        prm->time_budget != 0.0)
+        return CNMF_EINVAL;
     for (int i = 0; i < count; ++i) {
         const cnmf_instance& in = inst[i];
         cnmf_params pi = *prm;

@@ -97,6 +97,12 @@ inline int check_params(const cnmf_params* prm, int64_t n, int64_t m, bool need_
     if (prm->stop_rule != CNMF_STOP_GLOBAL && prm->stop_rule != CNMF_STOP_SUBPROBLEM)
         return CNMF_EINVAL;
     if (prm->sweep_prec != CNMF_PREC_FP32 && prm->sweep_prec != CNMF_PREC_BF16) return CNMF_EINVAL;
+    if (prm->solver != CNMF_SOLVER_NESTEROV && prm->solver != CNMF_SOLVER_HALS &&
+        prm->solver != CNMF_SOLVER_MU)
+        return CNMF_EINVAL;
+    if (prm->restart != CNMF_RESTART_NONE && prm->restart != CNMF_RESTART_GRADIENT) return CNMF_EINVAL;
+    if (prm->restart != CNMF_RESTART_NONE && prm->solver != CNMF_SOLVER_NESTEROV) return CNMF_EINVAL;
+    if (!(prm->time_budget >= 0.0) || prm->time_budget > 1e6) return CNMF_EINVAL;
     return CNMF_OK;
 }
 

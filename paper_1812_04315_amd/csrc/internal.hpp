@@ -23,6 +23,9 @@ struct Control {
     int pad0;
     double pg2[4];        // scratch for initial projected-gradient norms
     double tol[2];        // running gradient bounds (G, F) of the global rule
+    unsigned long long deadline;   // wall clock at which a time-budgeted outer loop stops
+    int stop;             // set once the deadline has passed: later phases do nothing
+    int pad1;
 };
 
 // Spin limit of a grid barrier: about a second of polling before the
@@ -364,6 +367,15 @@ struct PhaseArgs {
     double* eig_out;         // {L, v[32]} of this subproblem (written by block 0), or null
     float* hist;
     unsigned long long* tick_out;
+    float* w_out;            // p x p: W as used by this subproblem (block 0), or null
+    // time budget: a phase does nothing once *stop_flag is set; block 0 of a
+    // phase with done_out writes done_value there when it completes and, with
+    // deadline, sets *stop_flag when the wall clock has passed *deadline
+    int* stop_flag;
+    int32_t* done_out;
+    int done_value;
+    const unsigned long long* deadline;
+    int solver;              // kSolver*: update rule of the subproblem
 };
 
 // Batched launch of many subproblems (see k_phase_batched): args[count] on
@@ -384,7 +396,7 @@ bool phase_grid(const Dev& d, int64_t rows, int* tiles, unsigned* nblk);
 hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles);
 constexpr int kPgSlots = 10;   // slots per workgroup for projected-gradient partials
 constexpr size_t kPgWords = 8192;   // projected-gradient exchange words
-// Momentum weights of the inner loop (Algorithm 2): alpha_0 = 1,
+// Momentum weights of the inner loop (Sec. 2): alpha_0 = 1,
 // alpha_{k+1} = (1 + sqrt(4 alpha_k^2 + 1)) / 2, and inner step K uses
 // beta = (alpha_{K-2} - 1) / alpha_{K-1} (0 for K <= 2), rounded to FP32.  They
 // depend on K alone, so one table (host-made, FP64 recursion) serves every
@@ -401,12 +413,29 @@ inline void momentum_table(float* out, int n) {
     }
 }
 constexpr size_t kSlotWords = 1024 + kPgWords;
+// Update rules of a phase (PhaseArgs::solver): the Nesterov loop of Sec. 2,
+// the same with adaptive restart, HALS sweeps, multiplicative updates.
+constexpr int kSolverNesterov = 0;
+constexpr int kSolverHals = 1;
+constexpr int kSolverMu = 2;
+constexpr int kSolverRestart = 3;
+constexpr int kBetaLds = 1024;   // momentum weights a restarted loop keeps in LDS
 constexpr int kGrouped = 8;     // stop-test lag value selecting the grouped exchange
 constexpr int kEigWords = 33;   // {L, v[32]} per side and parity
 
 // misc kernels (small.hip)
 hipError_t write_tick(const Dev& d, unsigned long long* tick);
+// ctl->deadline = now + ticks, ctl->stop = 0 (start of a time-budgeted loop)
+hipError_t arm_deadline(const Dev& d, Control* ctl, unsigned long long ticks);
 hipError_t fill_u64(const Dev& d, uint64_t* p, int64_t count, uint64_t value);
+hipError_t fill_i32(const Dev& d, int32_t* p, int64_t count, int32_t value);
+// dst = scale * src over a rows x cols block (src may be dst)
+hipError_t scale2d(const Dev& d, int64_t rows, int64_t cols, const float* src, int64_t lds,
+                   float* dst, int64_t ldd, float scale);
+// A /= ||A||_F (FP64 sum of squares; part: kNormBlocks doubles of scratch)
+constexpr int kNormBlocks = 256;
+hipError_t normalize2d(const Dev& d, int64_t rows, int64_t cols, float* A, int64_t lda,
+                       double* part);
 hipError_t rre(const Dev& d, int64_t n, int64_t m, const float* X, int64_t ldx, int p,
                const float* G, int64_t sG, const float* F, int64_t sF, int count,
                double* out, double* partial, int64_t partial_len);

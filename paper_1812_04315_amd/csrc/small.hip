@@ -11,8 +11,20 @@ __global__ void k_fill_u64(uint64_t* p, int64_t count, uint64_t value) {
     if (i < count) p[i] = value;
 }
 
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
 __global__ void k_tick(unsigned long long* t) {
     if (threadIdx.x == 0) t[0] = wall_clock64();
+}
+
+__global__ void k_arm_deadline(Control* ctl, unsigned long long ticks) {
+    if (threadIdx.x == 0) {
+        ctl->deadline = wall_clock64() + ticks;
+        ctl->stop = 0;
+    }
 }
 
 // Residual ||X - G F||^2 (FP64 accumulation) for snapshot blockIdx.y over
@@ -73,6 +85,43 @@ __global__ void k_rre_final(int count, int nb, const double* __restrict__ part,
     out[i] = sqrt(s / x);
 }
 
+// dst = s * src over a rows x cols block (row pitches lds, ldd; src may be
+// dst).  s is the constant `scale`, or 1 / sqrt(sum of `np` partial sums)
+// when `part` is given (every thread sums the partials in the same order).
+__global__ void k_scale2d(int64_t rows, int64_t cols, const float* src, int64_t lds, float* dst,
+                          int64_t ldd, float scale, const double* part, int np) {
+    float sc = scale;
+    if (part) {
+        double t = 0.0;
+        for (int i = 0; i < np; ++i) t += part[i];
+        sc = t > 0.0 ? (float)(1.0 / sqrt(t)) : 1.f;
+    }
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / cols, c = e % cols;
+        dst[r * ldd + c] = sc * src[r * lds + c];
+    }
+}
+
+// part[block] = sum of squares of this block's share of a rows x cols block
+// (FP64, fixed order: repeatable)
+__global__ __launch_bounds__(256) void k_norm2_part(int64_t rows, int64_t cols, const float* A,
+                                                    int64_t lda, double* part) {
+    __shared__ double red[4];
+    const int64_t total = rows * cols;
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const double v = A[(e / cols) * lda + e % cols];
+        acc = fma(v, v, acc);
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 int64_t rre_blocks(const Dev& d, int64_t n) {
     int64_t b = (n + kRowsR * 4 - 1) / (kRowsR * 4);
     if (b > 2 * d.num_cus) b = 2 * d.num_cus;
@@ -86,9 +135,39 @@ hipError_t write_tick(const Dev& d, unsigned long long* tick) {
     return hipGetLastError();
 }
 
+hipError_t arm_deadline(const Dev& d, Control* ctl, unsigned long long ticks) {
+    hipLaunchKernelGGL(k_arm_deadline, dim3(1), dim3(64), 0, d.stream, ctl, ticks);
+    return hipGetLastError();
+}
+
+hipError_t scale2d(const Dev& d, int64_t rows, int64_t cols, const float* src, int64_t lds,
+                   float* dst, int64_t ldd, float scale) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale2d, dim3(256), dim3(256), 0, d.stream, rows, cols, src, lds, dst, ldd,
+                       scale, (const double*)nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t normalize2d(const Dev& d, int64_t rows, int64_t cols, float* A, int64_t lda,
+                       double* part) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_norm2_part, dim3(kNormBlocks), dim3(256), 0, d.stream, rows, cols, A, lda,
+                       part);
+    hipLaunchKernelGGL(k_scale2d, dim3(256), dim3(256), 0, d.stream, rows, cols, A, lda, A, lda,
+                       1.f, (const double*)part, kNormBlocks);
+    return hipGetLastError();
+}
+
 hipError_t fill_u64(const Dev& d, uint64_t* p, int64_t count, uint64_t value) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, d.stream, p,
+                       count, value);
+    return hipGetLastError();
+}
+
+hipError_t fill_i32(const Dev& d, int32_t* p, int64_t count, int32_t value) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, d.stream, p,
                        count, value);
     return hipGetLastError();
 }

@@ -62,6 +62,19 @@ __device__ __forceinline__ void settle(v4f& acc) { asm volatile("" : "+v"(acc));
 
 __device__ __forceinline__ int perm16(int m) { return 4 * (m & 3) + (m >> 2); }
 
+// Sum over the four lanes that hold one row (l, l ^ 16, l ^ 32, l ^ 48): the
+// row swap pairs 16-lane rows 0-1 and 2-3, the half swap the two halves;
+// both lanes of a pair add the same two values, so all four hold the same
+// bits.
+__device__ __forceinline__ float row_sum4(float v) {
+    const unsigned b = __float_as_uint(v);
+    const auto x = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+    const float s = __uint_as_float(x[0]) + __uint_as_float(x[1]);
+    const unsigned c = __float_as_uint(s);
+    const auto y = __builtin_amdgcn_permlane32_swap(c, c, false, false);
+    return __uint_as_float(y[0]) + __uint_as_float(y[1]);
+}
+
 __device__ __forceinline__ void slot_store(uint64_t* p, unsigned tag, uint32_t payload) {
     __hip_atomic_store(p, ((uint64_t)tag << 32) | payload, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
@@ -205,6 +218,24 @@ __device__ __forceinline__ double rayleigh(const double (&wr)[P], double v) {
     return num / den;
 }
 
+// Rayleigh quotient rho = v^T W v / v^T v and the squared residual
+// ||W v - rho v||^2 / v^T v, on every lane.
+template <int P>
+__device__ __forceinline__ double rayleigh_res(const double (&wr)[P], double v, double& res2) {
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < P; j += 2) {
+        t0 = fma(wr[j], lane_d(v, j), t0);
+        if (j + 1 < P) t1 = fma(wr[j + 1], lane_d(v, j + 1), t1);
+    }
+    const double wv = t0 + t1;                 // (W v)_lane; 0 on lanes >= p
+    const double den = wave_sum(v * v);
+    const double rho = wave_sum(v * wv) / den;
+    const double r = fma(-rho, v, wv);
+    res2 = wave_sum(r * r) / den;
+    return rho;
+}
+
 // v scaled to (about) unit length: only its direction is used
 __device__ __forceinline__ void normalise(double& v) {
     const double nn = wave_sum(v * v);
@@ -324,17 +355,21 @@ __device__ __forceinline__ int shifted_solve(const double (&wr)[P], double sigma
     }
 }
 
-// lambda_max of the symmetric W (p x p, FP64 in LDS) by one
-// wavefront, warm-started from the top eigenvector of the previous
-// subproblem of the same side (prev_L <= 0 means none; lane i < p holds its
-// component i in prev_v).  With rho0 the Rayleigh quotient of the start
-// vector (a lower bound), one factorisation of W - sigma I,
-// sigma = rho0 (1 + 1e-4), certifies by its inertia that every eigenvalue
-// lies below sigma and gives one inverse-iteration step with that shift; the
-// Rayleigh quotient of the result is L (between rho0 and sigma, and within
-// ~theta^2 of lambda_max for the remaining angle theta).  Without a usable
-// start, or when the certificate fails, the tridiagonalisation and
-// bisection above (on M, LDS) give L and one inverse-iteration step gives
+// lambda_max of the symmetric W (p x p, FP64 in LDS) by one wavefront,
+// warm-started from the top eigenvector of the previous subproblem of the
+// same side (prev_L <= 0 means none; lane i < p holds its component i in
+// prev_v).  One inverse-iteration step from that vector, with the shift
+// sigma = rho0 (1 + 1e-4) just above its Rayleigh quotient rho0 (FP32
+// elimination of W - sigma I), gives v; rho = Rayleigh(v) <= lambda_max.
+// The Kato-Temple inequality bounds the rest: if every other eigenvalue is
+// at most a < rho, then lambda_max <= rho + ||W v - rho v||^2 / (rho - a).
+// W is symmetric positive semidefinite up to the rounding of its entries,
+// so lambda_2 <= trace(W) - lambda_max + (rounding) <= trace(W) - rho + 1e-4
+// trace(W) = a.  When that bound is within 1e-12 rho of rho, L = the bound:
+// an upper bound of lambda_max within 1e-12 relative.  Otherwise (no start,
+// no separation of lambda_max from the rest, a vector not yet accurate
+// enough) the tridiagonalisation and bisection above (on M, LDS) give L, the
+// upper end of a bracket 1e-13 wide, and one inverse-iteration step gives
 // the vector.  On return v (lane-distributed) is the unit top eigenvector.
 template <int P>
 __device__ __forceinline__ double lambda_max_warm(const double (*W)[34], double (*M)[33], int p,
@@ -349,8 +384,12 @@ __device__ __forceinline__ double lambda_max_warm(const double (*W)[34], double 
         if (rho0 > 0.0 && rho0 < 1e300) {
             const int cnt = shifted_solve<P>(wr, rho0 * (1.0 + 1e-4), v, p);
             normalise(v);
-            const double rho = rayleigh<P>(wr, v);
-            if (cnt == p && rho >= rho0 * (1.0 - 1e-12) && rho < 1e300) return rho;
+            double res2 = 0.0;
+            const double rho = rayleigh_res<P>(wr, v, res2);
+            const double tr = wave_sum(lane < p ? W[lane][lane] : 0.0);
+            const double gap = rho - (tr - rho) - 1e-4 * fabs(tr);   // rho - a
+            if (cnt >= 0 && gap > 0.0 && rho < 1e300 && res2 <= 1e-12 * rho * gap)
+                return rho + res2 / gap;
         }
     }
     if (lane < p)
@@ -372,9 +411,16 @@ namespace {
 
 // One subproblem (G rows or F columns) on workgroup blk of nblk; seq tags
 // the exchange words of this launch.
-template <int PT, int TILES, int DLAG>
+// SOLVER: kSolverNesterov (Sec. 2), kSolverRestart (the same loop with the
+// momentum of every row restarted adaptively; non-grouped exchange only),
+// kSolverHals or kSolverMu (fixed counts of HALS sweeps or multiplicative
+// updates; no Lipschitz constant, no stopping test).
+template <int PT, int TILES, int DLAG, int SOLVER = kSolverNesterov>
 __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned blk,
                                            const unsigned nblk, const unsigned seq) {
+    constexpr bool ALT = SOLVER == kSolverHals || SOLVER == kSolverMu;
+    constexpr bool RESTART = SOLVER == kSolverRestart;
+    static_assert(!RESTART || DLAG != kGrouped, "restart runs the per-step exchange");
     // DLAG = kGrouped: the norms of GB consecutive steps travel in one
     // exchange, tested one group late; otherwise every step's norm is
     // exchanged and tested DLAG steps late.
@@ -400,13 +446,19 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     __shared__ int s_flag;
     __shared__ float zt[4][16][33];   // per-wave transpose tile
     __shared__ float sred[4][16][64]; // epilogue reduction
+    __shared__ float sbeta[RESTART ? kBetaLds : 1];   // momentum weights by a row's own step
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int q16 = lane & 15;
     const int g4 = lane >> 4;
     const int p = a.p;
+    // a time-budgeted loop whose deadline has passed: nothing left to do (the
+    // flag was written by an earlier launch, so every workgroup sees it)
+    if (a.stop_flag && *a.stop_flag) return;
     __syncthreads();   // LDS of a previous subproblem on this workgroup
+    if constexpr (RESTART)
+        for (int e = threadIdx.x; e < kBetaLds; e += kThreads) sbeta[e] = a.beta[e];
     Control* ctl = a.ctl;
     bool ok = true;
     // warm start of lambda_max (wave 0), fetched now so the load is in
@@ -557,7 +609,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             }
 
     double L = 1.0;
-    if (a.kind == 0 && wave == 0) {
+    if (!ALT && a.kind == 0 && wave == 0) {
         double ev;
         const double lm = lambda_max_warm<16 * PT>(sWd, sM, p, eig_L, eig_v, ev, swv, sdg, seo, sv);
         if (lane == 0) s_L = lm;
@@ -566,6 +618,8 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             if (lane < p) a.eig_out[1 + lane] = ev;
         }
     }
+    if (a.kind == 0 && a.w_out && blk == 0 && wave == 1)
+        for (int e = lane; e < p * p; e += 64) a.w_out[e] = sW[e / p][e % p];
 
     if (a.mode == 2) {
         // B rows = D S: A operand S[k][16h' + perm(m)], B operand D[r][k]
@@ -730,6 +784,89 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             for (int i = 0; i < NR; ++i) zh[j][t][i] = z[t][i];
     int out_idx = GROUPED ? -1 : 0;   // the grouped loop writes z itself
 
+    if constexpr (ALT) {
+        if (ok && kmax > 0) {
+            if constexpr (SOLVER == kSolverHals) {
+                // Coordinate j of a row lives in register j / 4 of the lane
+                // with g4 = j % 4 (column 4 r + g4 in register r); the row's
+                // four lanes add their shares of grad_j and the owner moves
+                // z_j to the minimiser along j, clipped at 0 (Gauss-Seidel:
+                // the next coordinate sees the new value).
+                for (int it = 0; it < kmax; ++it) {
+#pragma unroll
+                    for (int j = 0; j < 16 * PT; ++j) {
+                        if (j >= p) continue;   // uniform
+                        const int r = j >> 2;
+                        const bool own = g4 == (j & 3);
+                        const float wjj = sW[j][j];
+                        float ca[NR];
+#pragma unroll
+                        for (int rr = 0; rr < NR; ++rr)
+                            ca[rr] = a.wt ? sW[j][4 * rr + g4] : sW[4 * rr + g4][j];
+#pragma unroll
+                        for (int t = 0; t < TILES; ++t) {
+                            float dsum = 0.f;
+#pragma unroll
+                            for (int rr = 0; rr < NR; ++rr) dsum = fmaf(z[t][rr], ca[rr], dsum);
+                            dsum = row_sum4(dsum);
+#pragma unroll
+                            for (int rr = 0; rr < NR; ++rr) {
+                                if (rr != r) continue;
+                                if (own && wjj > 0.f) {
+                                    const float nz = z[t][rr] - (dsum - bb[t][rr]) / wjj;
+                                    z[t][rr] = (nz > 0.f || nz != nz) ? nz : 0.f;
+                                }
+                            }
+                        }
+                    }
+                }
+            } else {
+                // Z <- Z * sqrt((B+ + Z A-) / (B- + Z A+)) with A the operand
+                // of the gradient product (W, or W^T for F): both products on
+                // the matrix cores in the layout of Z.
+                float wAp[PT][PT][4], wAn[PT][PT][4];
+#pragma unroll
+                for (int hp = 0; hp < PT; ++hp)
+#pragma unroll
+                    for (int h = 0; h < PT; ++h)
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            wAp[hp][h][s] = fmaxf(wA[hp][h][s], 0.f);
+                            wAn[hp][h][s] = fmaxf(-wA[hp][h][s], 0.f);
+                        }
+                auto prod = [&](const float (&op)[PT][PT][4], const float (&zz)[NR], float (&o)[NR]) {
+#pragma unroll
+                    for (int hp = 0; hp < PT; ++hp) {
+                        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int h = 0; h < PT; ++h)
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) acc = mfma16(op[hp][h][s], zz[4 * h + s], acc);
+                        settle(acc);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) o[4 * hp + i] = acc[i];
+                    }
+                };
+                for (int it = 0; it < kmax; ++it) {
+#pragma unroll
+                    for (int t = 0; t < TILES; ++t) {
+                        float zp[NR], zm[NR];
+                        prod(wAp, z[t], zp);
+                        prod(wAn, z[t], zm);
+#pragma unroll
+                        for (int i = 0; i < NR; ++i) {
+                            const float num = fmaxf(bb[t][i], 0.f) + zm[i];
+                            const float den = fmaxf(-bb[t][i], 0.f) + zp[i];
+                            const float ratio = den > 0.f ? num / den : 1.f;
+                            z[t][i] *= sqrtf(ratio);
+                        }
+                    }
+                }
+            }
+        }
+        steps = kmax;
+        out_idx = -1;   // z holds the result
+    } else {
     if (!(L > 0.0)) {
         if (a.kind == 0 && blk == 0 && threadIdx.x == 0)
             raise_status(ctl, (L != L) ? CNMF_ST_NONFINITE : CNMF_ST_ZERO_LIPS);
@@ -977,6 +1114,12 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         constexpr bool CHECK = decltype(check_tag)::value;
         kend = CHECK ? kmax + DLAG : kmax;
         float beta_n = a.beta[1];   // step K + 1, fetched a step ahead
+        // restart: the step at which each row tile's momentum last restarted
+        // (the start counts as a restart at step 1); row r's point Y_K uses
+        // the weight of step K - k0 + 1 of a fresh loop
+        int k0[TILES];
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) k0[t] = 1;
         for (; K <= kend; ++K) {
             const int jst = K - DLAG;
             const bool test = CHECK && jst >= a.inner_min && jst <= kmax;
@@ -986,12 +1129,22 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 float zn[TILES][NR], gn[TILES][NR];
 #pragma unroll
                 for (int t = 0; t < TILES; ++t) {
+                    float bt = beta;
+                    if constexpr (RESTART) {
+                        const int bi = K - k0[t];
+                        bt = bi < kBetaLds ? sbeta[bi] : a.beta[bi];
+                    }
+                    float dr = 0.f;   // restart: (Y_K - Z_K) . (Z_K - Z_{K-1}) over the row
 #pragma unroll
                     for (int i = 0; i < NR; ++i) {
-                        const float y = fmaf(beta, zh[0][t][i] - zh[1][t][i], zh[0][t][i]);
-                        const float gy = fmaf(beta, g[t][i] - gp[t][i], g[t][i]);
+                        const float y = fmaf(bt, zh[0][t][i] - zh[1][t][i], zh[0][t][i]);
+                        const float gy = fmaf(bt, g[t][i] - gp[t][i], g[t][i]);
                         const float v = fmaf(-gy, invL, y);
                         zn[t][i] = (v > 0.f || v != v) ? v : 0.f;
+                        if constexpr (RESTART) dr = fmaf(y - zn[t][i], zn[t][i] - zh[0][t][i], dr);
+                    }
+                    if constexpr (RESTART) {
+                        if (row_sum4(dr) > 0.f) k0[t] = K;
                     }
                     grad(zn[t], bb[t], gn[t]);
                 }
@@ -1045,6 +1198,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         else run_steps(std::false_type{});
         }
     }
+    }   // !ALT
 
     // final iterate zh[out_idx] -> z
 #pragma unroll
@@ -1150,28 +1304,39 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 a.tol_init_out[1] = tt;
                 if (!isfinite(tt)) raise_status(ctl, CNMF_ST_NONFINITE);
             }
-            if (a.kind == 0 && a.tol_state && steps >= 1 && steps <= a.inner_min)
+            if (!ALT && a.kind == 0 && a.tol_state && steps >= 1 && steps <= a.inner_min)
                 a.tol_state[0] = tol / 10.0;
+            if (a.done_out) a.done_out[0] = a.done_value;
+            if (a.deadline && a.stop_flag && wall_clock64() > *a.deadline) *a.stop_flag = 1;
         }
         if (a.tick_out) atomicMax(a.tick_out, (unsigned long long)wall_clock64());
     }
 }
 
-template <int PT, int TILES, int DLAG>
+template <int PT, int TILES, int DLAG, int SOLVER = kSolverNesterov>
 __global__ __launch_bounds__(kThreads) void k_phase(PhaseArgs a) {
-    phase_body<PT, TILES, DLAG>(a, blockIdx.x, gridDim.x, a.seq);
+    phase_body<PT, TILES, DLAG, SOLVER>(a, blockIdx.x, gridDim.x, a.seq);
 }
 
-template <int PT, int TILES, int DLAG>
+template <int PT, int TILES, int DLAG, int SOLVER = kSolverNesterov>
 hipError_t launch3(const Dev& d, const PhaseArgs& a, unsigned nblk) {
-    hipLaunchKernelGGL((k_phase<PT, TILES, DLAG>), dim3(nblk), dim3(kThreads), 0, d.stream, a);
+    hipLaunchKernelGGL((k_phase<PT, TILES, DLAG, SOLVER>), dim3(nblk), dim3(kThreads), 0, d.stream,
+                       a);
     return hipGetLastError();
 }
 
 // Stop-test lag: -1 picks the grouped exchange when the iterate history
-// fits the registers (PT * TILES <= 2), else a lag of two steps.
+// fits the registers (PT * TILES <= 2), else a lag of two steps.  HALS and
+// multiplicative updates test nothing; the restarted loop exchanges every
+// step's norm, tested two steps late.
 template <int PT, int TILES>
 hipError_t launch2(const Dev& d, const PhaseArgs& a, unsigned nblk) {
+    switch (a.solver) {
+        case kSolverHals: return launch3<PT, TILES, 0, kSolverHals>(d, a, nblk);
+        case kSolverMu: return launch3<PT, TILES, 0, kSolverMu>(d, a, nblk);
+        case kSolverRestart: return launch3<PT, TILES, 2, kSolverRestart>(d, a, nblk);
+        default: break;
+    }
     int dl = a.dlag;
     if (dl < 0) dl = PT * TILES <= 2 ? kGrouped : 2;
     if (dl == kGrouped) {
@@ -1287,6 +1452,7 @@ hipError_t phase_batched(const Dev& d, const BatchLaunch& b, int tiles, int dlag
 hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles) {
     if (a.p < 1 || a.p > 32 || a.dlag < -1 || (a.dlag > 4 && a.dlag != kGrouped))
         return hipErrorInvalidValue;
+    if (a.solver < kSolverNesterov || a.solver > kSolverRestart) return hipErrorInvalidValue;
     if (a.p <= 16) return launch1<1>(d, a, tiles, nblk);
     return launch1<2>(d, a, tiles, nblk);
 }

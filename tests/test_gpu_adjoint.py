@@ -22,6 +22,11 @@ def _case(n, m, p, nu, seed):
     return inst, Gt, Ft
 
 
+def _loss64(G, F, Gt, Ft):
+    """||G - Gt||^2 + ||F - Ft||^2 summed in FP64 on the host."""
+    return float(np.sum((host(G) - Gt) ** 2) + np.sum((host(F) - Ft) ** 2))
+
+
 def _gpu_loss_grad(inst, Gt, Ft, q, T, K, ckpt):
     import torch
     X = dev(inst.X, (inst.X.shape[1] + 3) // 4 * 4)
@@ -75,7 +80,7 @@ def test_adjoint_matches_gpu_central_differences():
             G, F, tape = cnmf.adj_forward(dev(Xs, 152), dev(inst.omega_L), dev(inst.omega_R),
                                           dev(inst.G0), dev(inst.F0), p=p, nu=nu, q=q,
                                           outer_iters=T, inner_steps=K, ckpt=3)
-            vals.append(float(torch.sum((G - dev(Gt)) ** 2) + torch.sum((F - dev(Ft)) ** 2)))
+            vals.append(_loss64(G, F, Gt, Ft))
             tape.close()
         fd.append((vals[0] - vals[1]) / (2 * h))
         an.append(float(np.sum(gX * D)))
@@ -112,3 +117,65 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     c = _gpu_loss_grad(inst, Gt, Ft, 2, 8, 5, 3)
     for x, y in ((a, b), (a, c)):
         assert np.array_equal(x[1], y[1])
+
+
+def test_adjoint_refuses_replaced_basis_columns():
+    """Noiseless rank-5 data with l = 15: the rank rule replaces ten columns
+    of every panel, where the bases of Algorithm 2 have no derivative.  The
+    backward pass refuses (CNMF_ENODERIV), as the FP64 reference does."""
+    say("adjoint_refuses")
+    inst = synth.instance(200, 150, 5, 10, seed=0)
+    G, F, tape = cnmf.adj_forward(dev(inst.X, 152), dev(inst.omega_L), dev(inst.omega_R),
+                                  dev(inst.G0), dev(inst.F0), p=5, nu=10, q=2, outer_iters=3,
+                                  inner_steps=5, ckpt=1)
+    with pytest.raises(cnmf.CnmfError) as ei:
+        tape.backward(G * 0 + 1, F * 0 + 1)
+    assert ei.value.code == cnmf.ENODERIV
+    tape.close()
+    cnmf.check()
+    rng = np.random.default_rng(1)
+    with pytest.raises(ValueError):
+        oracle.adjoint.loss_grad(inst.X, inst.omega_L, inst.omega_R, inst.G0, inst.F0,
+                                 rng.random(inst.G0.shape), rng.random(inst.F0.shape), 2, 3, 5)
+
+
+def test_adjoint_central_differences_at_full_size():
+    """The differentiation form's own check: n = m = 2000, p = 10, l = 20,
+    q = 2, 30 dB, 50 outer iterations x 5 inner steps, checkpoints every 10;
+    32 directions D (||D|| = ||X||), h = 1e-3, on the GPU forward.  The
+    entries of the final factors whose zero pattern differs between X + hD
+    and X - hD (kinks of max(0, .) crossed inside the difference) are
+    counted and reported per direction."""
+    say("adjoint_fd_full")
+    n = m = 2000
+    p, nu, q, T, K, ck = 10, 10, 2, 50, 5, 10
+    inst, Gt, Ft = _case(n, m, p, nu, seed=0)
+    Lv, gX, _, _, _, _ = _gpu_loss_grad(inst, Gt, Ft, q, T, K, ck)
+    rng = np.random.default_rng(5)
+    X = inst.X.astype(np.float64)
+    nX = np.linalg.norm(X)
+    h = 1e-3
+    fd, an, flips = [], [], []
+    for j in range(32):
+        D = rng.standard_normal(X.shape)
+        D *= nX / np.linalg.norm(D)
+        vals, zeros = [], []
+        for sgn in (1.0, -1.0):
+            Xs = (X + sgn * h * D).astype(np.float32)
+            G, F, tape = cnmf.adj_forward(dev(Xs, 2048), dev(inst.omega_L), dev(inst.omega_R),
+                                          dev(inst.G0), dev(inst.F0), p=p, nu=nu, q=q,
+                                          outer_iters=T, inner_steps=K, ckpt=ck)
+            vals.append(_loss64(G, F, Gt, Ft))
+            zeros.append((host(G) == 0, host(F) == 0))
+            tape.close()
+        flips.append(int(np.sum(zeros[0][0] != zeros[1][0]) + np.sum(zeros[0][1] != zeros[1][1])))
+        fd.append((vals[0] - vals[1]) / (2 * h))
+        an.append(float(np.sum(gX * D)))
+    cnmf.check()
+    fd, an = np.array(fd), np.array(an)
+    cos = float(fd @ an / (np.linalg.norm(fd) * np.linalg.norm(an)))
+    rel = float(np.linalg.norm(fd - an) / np.linalg.norm(fd))
+    per = np.abs(fd - an) / np.abs(fd)
+    say("central differences: cosine", cos, "rel", rel, "per direction rel", np.round(per, 4).tolist(),
+        "flipped entries per direction", flips)
+    assert cos >= 0.999 and rel <= 1e-2, (cos, rel)

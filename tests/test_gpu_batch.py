@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import PARITY_RTOL, dev, host, rel_fro, say
+from gpu_util import PARITY_RTOL, dev, follow_decisions, host, rel_fro, say
 
 pytestmark = pytest.mark.gpu
 
@@ -73,20 +73,24 @@ def test_batch_stopping_rule_without_replay():
     T, K = 10, 60
     insts = [synth.instance(n, m, p, nu, seed=30 + k, snr_db=40.0)
              for k, (n, m, p, nu) in enumerate(SHAPES[:4])]
-    descs, refs = [], []
+    descs, comps = [], []
     for inst in insts:
         comp, comp32 = _shared(inst)
-        refs.append(oracle.nenmf(inst.X, inst.G0, inst.F0, T, K, compressed=comp32))
+        comps.append(comp32)
         descs.append(_desc(inst, comp, T))
     b = cnmf.Batch(descs, outer_iters=T, inner_max=K)
     b.solve(True)
     cnmf.check()
-    for d, ref in zip(descs, refs):
+    for d, inst, comp32 in zip(descs, insts, comps):
         steps = host(d["steps"]).astype(int)
-        assert np.abs(steps - ref.steps).max() <= 1
-        if np.array_equal(steps, ref.steps):
-            assert rel_fro(host(d["G"]), ref.G) <= PARITY_RTOL
-            assert rel_fro(host(d["F"]), ref.F) <= PARITY_RTOL
+        # the oracle's own decisions, following the GPU's only within the
+        # margin of the bound
+        ref, followed = follow_decisions(steps, lambda rep: oracle.nenmf(
+            inst.X, inst.G0, inst.F0, T, K, compressed=comp32, keep_pg=True, replay=rep))
+        if followed:
+            say("followed", followed)
+        assert rel_fro(host(d["G"]), ref.G) <= PARITY_RTOL
+        assert rel_fro(host(d["F"]), ref.F) <= PARITY_RTOL
     b.close()
 
 
