@@ -43,6 +43,8 @@ extern "C" {
 #define CNMF_ENODERIV   -5   /* cnmf_adj_backward(): the rank rule replaced a
                                 basis column, where the bases of Algorithm 2
                                 have no derivative                            */
+#define CNMF_ETOOBIG    -6   /* cnmf_solve_noalloc(): the problem needs more
+                                scratch than CNMF_NOALLOC_SCRATCH_BYTES       */
 
 /* ---- device status word bits (cnmf_status) ----------------------------- */
 #define CNMF_ST_NONFINITE   0x01  /* NaN/Inf met in data, a Gram or a norm     */
@@ -213,6 +215,32 @@ int cnmf_solve(cnmf_ctx* ctx, int method, int64_t n, int64_t m,
                const float* Q_L, const float* Q_R, const float* X_L,
                const float* X_R, const cnmf_params* prm, float* G, float* F,
                const cnmf_trace* trace, const int32_t* replay);
+
+/* cnmf_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results as cnmf_solve, but the call
+ * allocates nothing.  Its scratch (partial products of the phases, the
+ * warm-start vectors of lambda_max and, for the plain method, B = X F^T,
+ * G^T X and their split partial sums) lives in a static device array of
+ * CNMF_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs
+ * on until the process ends; its device address is looked up once per
+ * device by cnmf_create.  Limit: the compressed method always fits
+ * (n, m <= 65536 need at most 2 MiB); the plain method needs about
+ * 4 (n + m) p bytes plus the split sums of its two X sweeps (at most about
+ * 16 MiB on 256 compute units; 10000 x 10000 at p = 15 needs 17 MiB in
+ * all) and returns CNMF_ETOOBIG, enqueuing nothing, when that exceeds the
+ * array.  Every call on one GPU
+ * shares that GPU's array (whatever the context), and the array keeps the
+ * last call's contents (nothing in it needs clearing: every word is
+ * written before it is read within a call).  Calls that overlap on one GPU
+ * -- on different streams or from different threads -- race on it and must
+ * be serialised by the caller. */
+#define CNMF_NOALLOC_SCRATCH_BYTES (32u << 20)
+int cnmf_solve_noalloc(cnmf_ctx* ctx, int method, int64_t n, int64_t m,
+                       const float* X, int64_t ldx,
+                       const float* Q_L, const float* Q_R, const float* X_L,
+                       const float* X_R, const cnmf_params* prm, float* G, float* F,
+                       const cnmf_trace* trace, const int32_t* replay);
 
 /* Relative reconstruction error, Sec. 4, Eq. (4), for `count` factor pairs
  * G_i = G + i*strideG, F_i = F + i*strideF (element strides):

@@ -19,7 +19,8 @@ from dataclasses import dataclass
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcnmf.so")
 
-OK, EINVAL, ENOMEM, EHIP, EDEVICE, ENODERIV = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, EDEVICE, ENODERIV, ETOOBIG = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_SCRATCH_BYTES = 32 << 20
 ST_NONFINITE, ST_NEGATIVE, ST_BREAKDOWN, ST_ZERO_LIPS, ST_TIMEOUT = 1, 2, 4, 8, 16
 STOP_GLOBAL, STOP_SUBPROBLEM = 0, 1
 PREC_FP32, PREC_BF16 = 0, 1
@@ -33,7 +34,7 @@ EXPORTED = [
     "cnmf_params_default", "cnmf_strerror", "cnmf_create", "cnmf_destroy",
     "cnmf_set_stream", "cnmf_clock_hz", "cnmf_status", "cnmf_rsi", "cnmf_rsi_bf16",
     "cnmf_compress",
-    "cnmf_to_bf16", "cnmf_solve", "cnmf_rre", "cnmf_sweep_right", "cnmf_sweep_left",
+    "cnmf_to_bf16", "cnmf_solve", "cnmf_solve_noalloc", "cnmf_rre", "cnmf_sweep_right", "cnmf_sweep_left",
     "cnmf_sweep_right_bf16", "cnmf_sweep_left_bf16",
     "cnmf_orth", "cnmf_lipschitz", "cnmf_nnls",
     "cnmf_batch_create", "cnmf_batch_destroy", "cnmf_batch_rsi", "cnmf_batch_tune",
@@ -106,6 +107,9 @@ def lib() -> ctypes.CDLL:
                                              P, P, P, P]),
             "cnmf_solve": (ctypes.c_int, [P, ctypes.c_int, I64, I64, P, I64, P, P, P, P,
                                           ctypes.POINTER(Params), P, P, ctypes.POINTER(Trace), P]),
+            "cnmf_solve_noalloc": (ctypes.c_int, [P, ctypes.c_int, I64, I64, P, I64, P, P, P, P,
+                                                  ctypes.POINTER(Params), P, P,
+                                                  ctypes.POINTER(Trace), P]),
             "cnmf_rre": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, P, I64, I32, P]),
             "cnmf_sweep_right": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, I32, P, I64]),
             "cnmf_sweep_left": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, P, I64, I32]),
@@ -344,10 +348,12 @@ def solve(G, F, *, X=None, compressed=None, p: int | None = None, nu: int = 10,
           outer_iters: int = 200, inner_max: int = 500, inner_min: int = 1,
           inner_ratio: float = 1e-3, stop_rule: int = STOP_GLOBAL, trace: SolveTrace | None = None,
           replay=None, solver: int = SOLVER_NESTEROV, restart: int = RESTART_NONE,
-          time_budget: float = 0.0):
+          time_budget: float = 0.0, noalloc: bool = False):
     """NeNMF outer loop in place on G (n x p) and F (p x m).  Plain when
     ``compressed`` is None (needs X), else ``compressed = (Q_L, Q_R, X_L, X_R)``
-    from ``rsi`` (or any other compression of the same shapes)."""
+    from ``rsi`` (or any other compression of the same shapes).  ``noalloc``
+    calls the entry point that allocates no device memory (its scratch is the
+    library's static array on each GPU)."""
     torch = _torch()
     n, pp = G.shape
     p = pp if p is None else p
@@ -378,7 +384,7 @@ def solve(G, F, *, X=None, compressed=None, p: int | None = None, nu: int = 10,
         tr = Trace(*[ctypes.c_void_p(0 if t is None else t.data_ptr()) for t in
                      (trace.steps, trace.lips, trace.tols, trace.ticks, trace.G_hist, trace.F_hist,
                       trace.W_hist, trace.outer_done)])
-    _call("cnmf_solve", context().h, method, n, m,
+    _call("cnmf_solve_noalloc" if noalloc else "cnmf_solve", context().h, method, n, m,
           _ptr(X), _ld(X) if X is not None else m,
           _ptr(QL), _ptr(QR), _ptr(XL), _ptr(XR), ctypes.byref(prm), _ptr(G), _ptr(F),
           ctypes.byref(tr) if tr is not None else None, _ptr(replay))

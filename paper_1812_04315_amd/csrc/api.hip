@@ -8,9 +8,14 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "ctx.hpp"
+
+namespace {
+int scratch_address(int device, char** out);   // below, beside the scratch it serves
+}
 
 extern "C" {
 
@@ -38,6 +43,7 @@ const char* cnmf_strerror(int code) {
         case CNMF_EHIP: return "HIP runtime error";
         case CNMF_EDEVICE: return "device reported an error (see status word)";
         case CNMF_ENODERIV: return "no derivative: the rank rule replaced a basis column";
+        case CNMF_ETOOBIG: return "the problem needs more than the no-alloc scratch holds";
         default: return "unknown error";
     }
 }
@@ -99,6 +105,17 @@ int cnmf_create(cnmf_ctx** out, int device, void* stream) {
             if (c->beta) (void)hipFree(c->beta);
             delete c;
             return CNMF_ENOMEM;
+        }
+    }
+    {   // the device's copy of the no-alloc scratch (device current)
+        const int src = scratch_address(device, &c->scratch);
+        if (src) {
+            (void)hipFree(c->ctl);
+            (void)hipFree(c->slots);
+            (void)hipFree(c->oxch);
+            (void)hipFree(c->beta);
+            delete c;
+            return src;
         }
     }
     if (const char* e = std::getenv("CNMF_DLAG")) {
@@ -531,7 +548,33 @@ int cnmf_to_bf16(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t ldx,
 
 }  // extern "C"
 
+// Scratch of cnmf_solve_noalloc: device memory of the library itself, one
+// copy per GPU (each device holds it from the load of the library until the
+// process ends).  Host code never passes `scratch` itself to a kernel (in
+// host code the name is only a stand-in for the device symbol): every use
+// goes through the address hipGetSymbolAddress returned for the device,
+// kept in g_scratch by scratch_address().
+static __device__ __align__(256) char scratch[CNMF_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (current), looked up once per
+// device.
+int scratch_address(int device, char** out) {
+    if (device < 0 || device >= kMaxDevices) return CNMF_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return CNMF_EHIP;
+        g_scratch[device] = static_cast<char*>(ptr);
+    }
+    *out = g_scratch[device];
+    return CNMF_OK;
+}
 
 // The outer loop of cnmf_solve.  ws: workspace base of at least `cap`
 // bytes, or null for the context's (growing) workspace.
@@ -569,7 +612,7 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
                                                             sweep_left_partial_floats(c->dev, n, m)));
     const size_t o_eig = ar.take<double>(4 * kEigWords);   // {L, v} per side and parity
     if (ws) {
-        if (ar.off > cap) return CNMF_EINVAL;
+        if (ar.off > cap) return CNMF_ETOOBIG;
     } else {
         rc = ensure_ws(c, ar.off);
         if (rc) return rc;
@@ -728,6 +771,15 @@ int cnmf_solve(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X, in
                const int32_t* replay) {
     return solve_run(c, nullptr, 0, method, n, m, X, ldx, Q_L, Q_R, X_L, X_R, prm, G, F, trace,
                      replay);
+}
+
+int cnmf_solve_noalloc(cnmf_ctx* c, int method, int64_t n, int64_t m, const float* X,
+                       int64_t ldx, const float* Q_L, const float* Q_R, const float* X_L,
+                       const float* X_R, const cnmf_params* prm, float* G, float* F,
+                       const cnmf_trace* trace, const int32_t* replay) {
+    if (!c || !c->scratch) return CNMF_EINVAL;
+    return solve_run(c, c->scratch, CNMF_NOALLOC_SCRATCH_BYTES, method, n, m, X, ldx, Q_L, Q_R,
+                     X_L, X_R, prm, G, F, trace, replay);
 }
 
 int cnmf_rre(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t ldx, int32_t p,

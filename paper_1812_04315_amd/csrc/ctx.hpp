@@ -21,6 +21,7 @@ struct cnmf_ctx {
     int dlag = -1;                // stop-test lag (-1: automatic, see the phase launcher)
     char* ws = nullptr;           // device workspace
     size_t ws_bytes = 0;
+    char* scratch = nullptr;      // device address of this device's no-alloc scratch
     double clock_hz = 1e8;
 };
 
