@@ -451,7 +451,7 @@ def nenmf(X, G0, F0, outer_iters: int, inner_max: int, inner_min: int = 1,
           ratio: float = 1e-3, stop_rule: str = STOP_GLOBAL,
           compressed: RSIResult | None = None, replay=None,
           keep_history: bool = False, keep_pg: bool = False,
-          solver: str = "nesterov", restart: bool = False) -> NeNMFResult:
+          solver: str = "nesterov", restart: bool = False, on_outer=None) -> NeNMFResult:
     """Plain NeNMF (Sec. 2) or, given RSI output, compressed NeNMF (Algorithm 1).
 
     Each outer iteration updates G (Eq. (2)) and then F (Eq. (3)) with one
@@ -471,6 +471,7 @@ def nenmf(X, G0, F0, outer_iters: int, inner_max: int, inner_min: int = 1,
     ``solver``: "nesterov" (Sec. 2), or "hals" / "mu", which take exactly
     inner_max updates per subproblem (or the replayed count) and no bound.
     ``restart``: adaptive restart of the Nesterov loops (see nesterov_nnls).
+    ``on_outer(t, G, F)`` is called after every outer iteration (timing).
     """
     X = None if X is None else np.asarray(X, dtype=F64)
     G = np.asarray(G0, dtype=F64).copy()
@@ -546,6 +547,8 @@ def nenmf(X, G0, F0, outer_iters: int, inner_max: int, inner_min: int = 1,
             hist.append((G.copy(), F.copy()))
         if keep_pg:
             pgs.append((tr_g, tr_f))
+        if on_outer is not None:
+            on_outer(t, G, F)
     return NeNMFResult(G=G, F=F, steps=steps, lips=lips, tols=tols, tol0=tol0,
                        history=hist, pg=pgs)
 

@@ -277,17 +277,12 @@ hipError_t enqueue(const cnmf_batch* b, const Dev& d, const PhaseArgs* args, int
     return hipSuccess;
 }
 
-// Panels of one orthonormalisation launch: workgroups per panel in
-// proportion to its rows so that all panels fit one round of `slots`.
+// Workgroups per panel of one orthonormalisation launch: one per 256 rows
+// (orth_batch_blocks), the panels packed into rounds of `slots`.
 std::vector<unsigned> orth_share(const std::vector<int64_t>& rows, int slots) {
-    int64_t tot = 0;
-    for (int64_t r : rows) tot += r;
     std::vector<unsigned> nb;
-    for (int64_t r : rows) {
-        int64_t v = (int64_t)((double)r * slots / (double)(tot > 0 ? tot : 1));
-        v = std::min<int64_t>(v, (int64_t)orth_batch_blocks(r));
-        nb.push_back((unsigned)std::max<int64_t>(1, v));
-    }
+    for (int64_t r : rows)
+        nb.push_back(std::min<unsigned>(orth_batch_blocks(r), (unsigned)std::max(1, slots)));
     return nb;
 }
 
