@@ -55,6 +55,12 @@ extern "C" {
 
 /* ---- limits ---------------------------------------------------------- */
 #define CNMF_MAX_RANK    32   /* p and l = p + nu are at most 32              */
+#define CNMF_MAX_ROWS    65536 /* n and m of a solve (and of cnmf_nnls's rows):
+                                  every subproblem runs in one launch whose
+                                  workgroups (64 to 256 rows each, at most 256)
+                                  must all be resident on the GPU at once;
+                                  larger n or m is rejected with CNMF_EINVAL.
+                                  The RSI and the sweeps have no such limit. */
 
 /* ---- parameters ------------------------------------------------------ */
 #define CNMF_STOP_GLOBAL      0  /* tol = ratio * ||(P grad_G, P grad_F)|| at (G0,F0); /10 rule */
@@ -202,6 +208,8 @@ int cnmf_to_bf16(cnmf_ctx* ctx, int64_t n, int64_t m, const float* X,
 
 /* NeNMF outer loop: plain (Sec. 2, needs X) or compressed (Algorithm 1,
  * needs Q_L, Q_R, X_L, X_R from cnmf_rsi; X may then be NULL).
+ *   n, m <= CNMF_MAX_ROWS.  Results are bitwise repeatable: every reduction
+ *   (split sums, workgroup exchanges, norms) runs in a fixed order.
  *   G  in/out n x p (ld = p), F in/out p x m (ld = m); G0, F0 >= 0.
  *   trace  optional (host struct of device pointers), may be NULL.
  *   replay optional device int32 T x 2: run exactly these inner step counts

@@ -535,8 +535,27 @@ class Batch:
 
     def __init__(self, instances, *, q: int = 2, outer_iters: int = 100, inner_max: int = 500,
                  inner_min: int = 1, inner_ratio: float = 1e-3, stop_rule: int = STOP_GLOBAL,
-                 tau2: float = 1e-9, tiles_g: int = 0, tiles_f: int = 0):
+                 tau2: float = 1e-9, tiles_g: int = 0, tiles_f: int = 0, tune_cache=None):
+        """``tune_cache``: path of a JSON table of tuned tile shapes, keyed by
+        the device and the batch's shapes and loop settings; a known key
+        supplies tiles_g / tiles_f, and ``tune`` records its result there."""
         self._keep = list(instances)
+        self._cache = tune_cache
+        self._key = None
+        if tune_cache is not None:
+            import hashlib
+            import json
+            torch = _torch()
+            sig = [torch.cuda.get_device_name(), q, outer_iters, inner_max, inner_min, inner_ratio,
+                   stop_rule, [(int(d["G"].shape[0]), int(d["F"].shape[1]), int(d["p"]), int(d["nu"]))
+                               for d in instances]]
+            self._key = hashlib.sha256(json.dumps(sig).encode()).hexdigest()[:32]
+            if tiles_g == 0 and tiles_f == 0 and os.path.exists(tune_cache):
+                with open(tune_cache) as fh:
+                    hit = json.load(fh).get(self._key)
+                if hit:
+                    tiles_g, tiles_f = int(hit[0]), int(hit[1])
+        self.tiles = (tiles_g, tiles_f)
         arr = (Instance * len(instances))()
         for k, d in enumerate(instances):
             G, F = d["G"], d["F"]
@@ -562,9 +581,23 @@ class Batch:
         _call("cnmf_batch_rsi", self.h)
 
     def tune(self, iters: int = 3):
+        """Time every tile shape on scratch copies, keep the fastest (and
+        record it in the tune cache, if one was given)."""
         out = (ctypes.c_int32 * 2)()
         _call("cnmf_batch_tune", self.h, iters, out)
-        return int(out[0]), int(out[1])
+        self.tiles = (int(out[0]), int(out[1]))
+        if self._cache is not None:
+            import json
+            table = {}
+            if os.path.exists(self._cache):
+                with open(self._cache) as fh:
+                    table = json.load(fh)
+            table[self._key] = list(self.tiles)
+            tmp = f"{self._cache}.tmp{os.getpid()}"
+            with open(tmp, "w") as fh:
+                json.dump(table, fh, indent=1)
+            os.replace(tmp, self._cache)
+        return self.tiles
 
     def solve(self, use_graph: bool = True):
         _call("cnmf_batch_solve", self.h, 1 if use_graph else 0)

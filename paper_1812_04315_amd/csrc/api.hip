@@ -272,7 +272,7 @@ int cnmf_nnls(cnmf_ctx* c, int64_t rows, int32_t p, float* Z, int64_t z_rs, int6
     if (inner_max < 1 || inner_max > 100000 || inner_min < 1) return CNMF_EINVAL;
     int tiles = 0;
     unsigned nblk = 0;
-    if (!phase_grid(c->dev, rows, &tiles, &nblk)) return CNMF_EINVAL;
+    if (rows > CNMF_MAX_ROWS || !phase_grid(c->dev, rows, &tiles, &nblk)) return CNMF_EINVAL;
     if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
     PhaseArgs a{};
     a.rows = rows;
@@ -595,6 +595,7 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
     }
     int tilesG = 0, tilesF = 0;
     unsigned nbG = 0, nbF = 0;
+    if (n > CNMF_MAX_ROWS || m > CNMF_MAX_ROWS) return CNMF_EINVAL;
     if (!phase_grid(c->dev, n, &tilesG, &nbG) || !phase_grid(c->dev, m, &tilesF, &nbF))
         return CNMF_EINVAL;
     const int p = prm->p;

@@ -221,3 +221,27 @@ def test_batch_rsi_noiseless_bases_match_oracle():
         for key, r in (("Q_L", ref.Q_L), ("Q_R", ref.Q_R), ("X_L", ref.X_L), ("X_R", ref.X_R)):
             assert rel_fro(host(d[key]), r) <= PARITY_RTOL, key
     b.close()
+
+
+def test_tuned_tiles_persist(tmp_path):
+    """cnmf_batch_tune's choice is recorded in a JSON table keyed by device,
+    shapes and loop settings, and a later batch of the same shapes starts
+    from it without tuning again."""
+    say("batch_tune_cache")
+    T, K = 4, 30
+    insts = [synth.instance(n, m, p, nu, seed=60 + k, snr_db=30.0)
+             for k, (n, m, p, nu) in enumerate(SHAPES[:3])]
+    cache = str(tmp_path / "tiles.json")
+    descs = [_desc(inst, _shared(inst)[0], T) for inst in insts]
+    b = cnmf.Batch(descs, outer_iters=T, inner_max=K, tune_cache=cache)
+    tiles = b.tune(2)
+    b.close()
+    import json
+    table = json.load(open(cache))
+    assert list(table.values()) == [list(tiles)]
+    b2 = cnmf.Batch([_desc(inst, _shared(inst)[0], T) for inst in insts], outer_iters=T,
+                    inner_max=K, tune_cache=cache)
+    assert b2.tiles == tiles
+    b2.solve(True)
+    cnmf.check()
+    b2.close()

@@ -205,3 +205,37 @@ def test_invalid_arguments_rejected():
     assert ei.value.code == cnmf.EINVAL
     with pytest.raises(cnmf.CnmfError):             # q = 0
         cnmf.rsi(X, dev(inst.omega_L), dev(inst.omega_R), 3, 2, 0)
+
+
+@pytest.mark.parametrize("method", ["plain", "compressed"])
+def test_solve_bitwise_repeatable(method):
+    """Every reduction runs in a fixed order: two free-running solves on the
+    same inputs give the same bits (factors, step counts, bounds)."""
+    say("repeatable", method)
+    inst = synth.instance(2000, 1500, 12, 10, seed=8, snr_db=30.0)
+    X = dev(inst.X)
+    comp = None
+    if method == "compressed":
+        comp = cnmf.rsi(X, dev(inst.omega_L), dev(inst.omega_R), 12, 10, 4)
+    runs = []
+    for _ in range(2):
+        G, F, tr = _solve_gpu(inst, X, comp, 25, 500)
+        runs.append((host(G), host(F), host(tr.steps), host(tr.tols), host(tr.lips)))
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
+def test_rows_beyond_the_limit_rejected():
+    """n or m above CNMF_MAX_ROWS: CNMF_EINVAL before anything is enqueued
+    (the buffers are never read)."""
+    say("max_rows")
+    import torch
+    n, m, p, nu = 70000, 40, 3, 2
+    G = torch.zeros(n, p, device="cuda")
+    F = torch.zeros(p, m, device="cuda")
+    comp = (torch.zeros(n, p + nu, device="cuda"), torch.zeros(m, p + nu, device="cuda"),
+            torch.zeros(p + nu, m, device="cuda"), torch.zeros(n, p + nu, device="cuda"))
+    with pytest.raises(cnmf.CnmfError) as ei:
+        cnmf.solve(G, F, compressed=comp, p=p, outer_iters=1, inner_max=5)
+    assert ei.value.code == cnmf.EINVAL
+    assert cnmf.check() == 0
