@@ -113,91 +113,71 @@ __global__ __launch_bounds__(64) void k_tri_inv(int l, const float* R, float* Ri
 }
 
 // Unit eigenvector of the symmetric p x p W for its largest eigenvalue L, by
-// inverse iteration with the shift L (1 + 1e-9) in FP64 (Gaussian
-// elimination with partial pivoting, one wavefront, lane = row).
+// two steps of inverse iteration with the shift sigma = L (1 + 1e-9) in
+// FP64.  L is an upper bound of lambda_max, so W - sigma I is negative
+// definite and Gaussian elimination without pivoting is stable; one
+// wavefront, lane i keeps row i in registers, the pivot row of step k is
+// read from lane k.  The sign is fixed so that the largest component is
+// positive.
+template <int P>
 __global__ __launch_bounds__(64) void k_eigvec(int p, const float* W, const double* Lp, float* v) {
-    __shared__ double A[32][33];
-    __shared__ double x[32];
-    __shared__ int piv;
     const int lane = threadIdx.x;
     const double L = *Lp;
     const double sigma = L * (1.0 + 1e-9) + 1e-300;
-    if (lane < p) x[lane] = 1.0 / sqrt((double)p);
-    __syncthreads();
-    for (int it = 0; it < 3; ++it) {
-        for (int e = lane; e < p * p; e += 64) {
-            const int i = e / p, j = e % p;
-            A[i][j] = 0.5 * ((double)W[i * p + j] + (double)W[j * p + i]) - (i == j ? sigma : 0.0);
+    double x = lane < p ? 1.0 / sqrt((double)p) : 0.0;
+    for (int it = 0; it < 2; ++it) {
+        double R[P];
+#pragma unroll
+        for (int c = 0; c < P; ++c)
+            R[c] = (lane < p && c < p)
+                       ? 0.5 * ((double)W[lane * p + c] + (double)W[c * p + lane]) - (lane == c ? sigma : 0.0)
+                       : (lane == c ? 1.0 : 0.0);
+        double inv_own = 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double dk = lane_d(R[k], k);
+            if (dk == 0.0) dk = -1e-300;
+            const double inv = 1.0 / dk;
+            if (lane == k) inv_own = inv;
+            const double f = (lane > k && lane < P) ? R[k] * inv : 0.0;
+            x = fma(-f, lane_d(x, k), x);
+#pragma unroll
+            for (int c = k + 1; c < P; ++c) R[c] = fma(-f, lane_d(R[c], k), R[c]);
         }
-        __syncthreads();
-        // forward elimination with partial pivoting on [A | x]
-        for (int k = 0; k < p; ++k) {
-            if (lane == 0) {
-                int best = k;
-                for (int i = k + 1; i < p; ++i)
-                    if (fabs(A[i][k]) > fabs(A[best][k])) best = i;
-                piv = best;
-            }
-            __syncthreads();
-            const int pr = piv;
-            if (pr != k) {
-                if (lane <= p) {
-                    const int j = lane;
-                    if (j < p) {
-                        const double t = A[k][j];
-                        A[k][j] = A[pr][j];
-                        A[pr][j] = t;
-                    } else {
-                        const double t = x[k];
-                        x[k] = x[pr];
-                        x[pr] = t;
-                    }
-                }
-            }
-            __syncthreads();
-            double akk = A[k][k];
-            if (akk == 0.0) akk = 1e-300;
-            if (lane > k && lane < p) {
-                const double f = A[lane][k] / akk;
-                for (int j = k; j < p; ++j) A[lane][j] -= f * A[k][j];
-                x[lane] -= f * x[k];
-            }
-            __syncthreads();
+        // back substitution: lane i keeps row i of the upper factor
+        double xi = 0.0, acc = x;
+#pragma unroll
+        for (int k = P - 1; k >= 0; --k) {
+            const double xk = lane_d(acc * inv_own, k);
+            if (lane == k) xi = xk;
+            if (lane < k) acc = fma(-R[k], xk, acc);
         }
-        // back substitution (lane 0), then normalise
-        if (lane == 0) {
-            for (int i = p - 1; i >= 0; --i) {
-                double s = x[i];
-                for (int j = i + 1; j < p; ++j) s -= A[i][j] * x[j];
-                double aii = A[i][i];
-                if (aii == 0.0) aii = 1e-300;
-                x[i] = s / aii;
-            }
-            double nrm = 0.0;
-            for (int i = 0; i < p; ++i) nrm += x[i] * x[i];
-            nrm = sqrt(nrm);
-            // fix the sign: largest component positive
-            int big = 0;
-            for (int i = 1; i < p; ++i)
-                if (fabs(x[i]) > fabs(x[big])) big = i;
-            const double sg = x[big] < 0.0 ? -1.0 : 1.0;
-            for (int i = 0; i < p; ++i) x[i] = sg * x[i] / (nrm > 0.0 ? nrm : 1.0);
-        }
-        __syncthreads();
+        x = lane < p ? xi : 0.0;
+        const double nrm = sqrt(wave_sum(x * x));
+        x = nrm > 0.0 ? x / nrm : 0.0;
     }
-    if (lane < p) v[lane] = (float)x[lane];
+    // sign: the component of largest magnitude positive (first of ties)
+    const double ax = lane < p ? fabs(x) : -1.0;
+    const double mx = wave_max(ax);
+    const unsigned long long at = __ballot(lane < p && ax == mx);
+    const int big = at ? __ffsll((long long)at) - 1 : 0;
+    const double sg = lane_d(x, big) < 0.0 ? -1.0 : 1.0;
+    if (lane < p) v[lane] = (float)(sg * x);
 }
 
 // ---------------------------------------------------------------------------
 // Reverse of one Nesterov subproblem over `rows` independent rows (Sec. 2):
 //   Y_k = Z_{k-1} + b_k (Z_{k-1} - Z_{k-2})   (Z_{-1} = Z_0, b_1 = b_2 = 0)
 //   V_k = Y_k - (Y_k W - b) / L,   Z_k = max(0, V_k),   k = 1..K.
-// Given Zbar = dL/dZ_K: Z0bar, Bbar (per row), Ys / Vbars (for
-// Wbar = -(1/L) sum_k Y_k^T Vbar_k) and per-block partials of
-// Lbar = sum_k <Vbar_k, Y_k - V_k> / L.
+// Given Zbar = dL/dZ_K: Z0bar, Bbar (per row), and per-workgroup partials of
+// Wbar = -(1/L) sum_k Y_k^T Vbar_k (before the 1/L) and of
+// Lbar = sum_k <Vbar_k, Y_k - V_k> / L.  One wavefront per workgroup, one
+// row per lane; the p x p partial of Y_k^T Vbar_k over the wavefront's 64
+// rows is formed through LDS at every step, in FP64 and in a fixed order.
 // ---------------------------------------------------------------------------
+constexpr int kAdjRows = 64;   // rows (lanes) per workgroup of the NNLS reverse
 struct AdjNnls {
-    int64_t rows;
+    int64_t rows, zs_rows;   // zs_rows: rows of the Zs tape (a multiple of kAdjRows)
     int p, K;
     const float* Z0;
     int64_t z_rs, z_cs;
@@ -208,142 +188,163 @@ struct AdjNnls {
     const float* Zbar;
     float* Z0bar;            // same strides as Z0
     float* Bbar;             // same strides as B
-    float* Zs;               // [K + 1][rows][32]
-    float* Ys;               // [K][rows][p]
-    float* Vb;               // [K][rows][p]
+    float* Zs;               // [K + 1][zs_rows][32]
+    double* Wpart;           // [gridDim.x][p][p]
     double* Lpart;           // [gridDim.x]
     float beta[kMaxK + 1];   // beta[k] = b_k, k = 1..K
 };
 
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_nnls_adj(AdjNnls a) {
+__global__ __launch_bounds__(kAdjRows) void k_nnls_adj(AdjNnls a) {
+    constexpr int NE = (P * P + kAdjRows - 1) / kAdjRows;   // W entries per lane
     __shared__ float sW[32][33];
-    __shared__ double sred[4];
+    __shared__ float sy[kAdjRows][P + 1], sv[kAdjRows][P + 1];
     const int p = a.p;
-    for (int e = threadIdx.x; e < p * p; e += kThreads) sW[e / p][e % p] = a.W[e];
+    const int lane = threadIdx.x;
+    for (int e = lane; e < p * p; e += kAdjRows) sW[e / p][e % p] = a.W[e];
     __syncthreads();
     const double Ld = *a.L;
     const float invL = (float)(1.0 / Ld);
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    double lbar = 0.0;
-    if (r < a.rows) {
-        float b[P], zc[P], zp[P];
+    const int64_t r = (int64_t)blockIdx.x * kAdjRows + lane;
+    const bool valid = r < a.rows;
+    // rows past the end run on zeros: every product below is then zero
+    float b[P], zc[P], zp[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        b[c] = (valid && c < p) ? a.B[r * a.b_rs + c * a.b_cs] : 0.f;
+        zc[c] = (valid && c < p) ? a.Z0[r * a.z_rs + c * a.z_cs] : 0.f;
+        zp[c] = zc[c];
+    }
+    auto zs = [&](int k) { return a.Zs + ((int64_t)k * a.zs_rows + r) * 32; };
+#pragma unroll
+    for (int c = 0; c < P; ++c) zs(0)[c] = zc[c];
+    // forward recompute, keeping Z_0 .. Z_K
+    for (int k = 1; k <= a.K; ++k) {
+        const float bk = a.beta[k];
+        float y[P], zn[P];
+#pragma unroll
+        for (int c = 0; c < P; ++c) y[c] = fmaf(bk, zc[c] - zp[c], zc[c]);
 #pragma unroll
         for (int c = 0; c < P; ++c) {
-            b[c] = c < p ? a.B[r * a.b_rs + c * a.b_cs] : 0.f;
-            zc[c] = c < p ? a.Z0[r * a.z_rs + c * a.z_cs] : 0.f;
+            float g = -b[c];
+#pragma unroll
+            for (int d = 0; d < P; ++d) g = fmaf(y[d], d < p && c < p ? sW[d][c] : 0.f, g);
+            const float v = fmaf(-g, invL, y[c]);
+            zn[c] = (v > 0.f || v != v) ? v : 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
             zp[c] = zc[c];
+            zc[c] = zn[c];
+            zs(k)[c] = zn[c];
         }
-        auto zs = [&](int k) { return a.Zs + ((int64_t)k * a.rows + r) * 32; };
+    }
+    // reverse: za = dL/dZ_k (complete), zb = dL/dZ_{k-1}, zq = dL/dZ_{k-2}
+    float za[P], zb[P], zq[P], bb[P];
 #pragma unroll
-        for (int c = 0; c < P; ++c) zs(0)[c] = zc[c];
-        // forward recompute, keeping Z_0 .. Z_K
-        for (int k = 1; k <= a.K; ++k) {
-            const float bk = a.beta[k];
-            float y[P], zn[P];
+    for (int c = 0; c < P; ++c) {
+        za[c] = (valid && c < p) ? a.Zbar[r * a.z_rs + c * a.z_cs] : 0.f;
+        zb[c] = 0.f;
+        zq[c] = 0.f;
+        bb[c] = 0.f;
+    }
+    double wacc[NE];
 #pragma unroll
-            for (int c = 0; c < P; ++c) y[c] = fmaf(bk, zc[c] - zp[c], zc[c]);
+    for (int j = 0; j < NE; ++j) wacc[j] = 0.0;
+    double lbar = 0.0;
+    for (int k = a.K; k >= 1; --k) {
+        const float bk = a.beta[k];
+        const float* z1 = zs(k - 1);
+        const float* z2 = zs(k >= 2 ? k - 2 : 0);
+        float y[P], vb[P];
 #pragma unroll
-            for (int c = 0; c < P; ++c) {
-                float g = -b[c];
-#pragma unroll
-                for (int d = 0; d < P; ++d) g = fmaf(y[d], d < p && c < p ? sW[d][c] : 0.f, g);
-                const float v = fmaf(-g, invL, y[c]);
-                zn[c] = (v > 0.f || v != v) ? v : 0.f;
-            }
-#pragma unroll
-            for (int c = 0; c < P; ++c) {
-                zp[c] = zc[c];
-                zc[c] = zn[c];
-                zs(k)[c] = zn[c];
-            }
-        }
-        // reverse: za = dL/dZ_k (complete), zb = dL/dZ_{k-1}, zq = dL/dZ_{k-2}
-        float za[P], zb[P], zq[P], bb[P];
+        for (int c = 0; c < P; ++c) y[c] = fmaf(bk, z1[c] - z2[c], z1[c]);
 #pragma unroll
         for (int c = 0; c < P; ++c) {
-            za[c] = c < p ? a.Zbar[r * a.z_rs + c * a.z_cs] : 0.f;
-            zb[c] = 0.f;
+            float g = -b[c];
+#pragma unroll
+            for (int d = 0; d < P; ++d) g = fmaf(y[d], d < p && c < p ? sW[d][c] : 0.f, g);
+            const float v = fmaf(-g, invL, y[c]);
+            vb[c] = (v > 0.f) ? za[c] : 0.f;
+            lbar += (double)vb[c] * (double)(y[c] - v);
+        }
+        // this step's Y^T Vbar over the workgroup's rows
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            sy[lane][c] = y[c];
+            sv[lane][c] = vb[c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+            const int e = lane + j * kAdjRows;
+            if (e < p * p) {
+                const int dd = e / p, cc = e - dd * p;
+                double s = 0.0;
+                for (int rr = 0; rr < kAdjRows; ++rr) s = fma((double)sy[rr][dd], (double)sv[rr][cc], s);
+                wacc[j] += s;
+            }
+        }
+        // ybar = vbar (I - W / L)^T, with V = Y (I - W/L) + b / L
+        float yb[P];
+#pragma unroll
+        for (int d = 0; d < P; ++d) {
+            float s = 0.f;
+#pragma unroll
+            for (int c = 0; c < P; ++c) s = fmaf(vb[c], d < p && c < p ? sW[d][c] : 0.f, s);
+            yb[d] = fmaf(-s, invL, vb[d]);
+        }
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            bb[c] = fmaf(vb[c], invL, bb[c]);
+            if (k >= 2) {
+                zb[c] = fmaf(1.f + bk, yb[c], zb[c]);
+                zq[c] = fmaf(-bk, yb[c], zq[c]);
+            } else {
+                zb[c] += yb[c];   // Z_{-1} is Z_0
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            za[c] = zb[c];
+            zb[c] = zq[c];
             zq[c] = 0.f;
-            bb[c] = 0.f;
         }
-        for (int k = a.K; k >= 1; --k) {
-            const float bk = a.beta[k];
-            const float* z1 = zs(k - 1);
-            const float* z2 = zs(k >= 2 ? k - 2 : 0);
-            float y[P], vb[P];
-#pragma unroll
-            for (int c = 0; c < P; ++c) y[c] = fmaf(bk, z1[c] - z2[c], z1[c]);
-#pragma unroll
-            for (int c = 0; c < P; ++c) {
-                float g = -b[c];
-#pragma unroll
-                for (int d = 0; d < P; ++d) g = fmaf(y[d], d < p && c < p ? sW[d][c] : 0.f, g);
-                const float v = fmaf(-g, invL, y[c]);
-                vb[c] = (v > 0.f) ? za[c] : 0.f;
-                lbar += (double)vb[c] * (double)(y[c] - v);
-            }
-            float* ys = a.Ys + ((int64_t)(k - 1) * a.rows + r) * p;
-            float* vs = a.Vb + ((int64_t)(k - 1) * a.rows + r) * p;
-            for (int c = 0; c < p; ++c) {
-                ys[c] = y[c];
-                vs[c] = vb[c];
-            }
-            // ybar = vbar (I - W / L)^T, with V = Y (I - W/L) + b / L
-            float yb[P];
-#pragma unroll
-            for (int d = 0; d < P; ++d) {
-                float s = 0.f;
-#pragma unroll
-                for (int c = 0; c < P; ++c) s = fmaf(vb[c], d < p && c < p ? sW[d][c] : 0.f, s);
-                yb[d] = fmaf(-s, invL, vb[d]);
-            }
-#pragma unroll
-            for (int c = 0; c < P; ++c) {
-                bb[c] = fmaf(vb[c], invL, bb[c]);
-                if (k >= 2) {
-                    zb[c] = fmaf(1.f + bk, yb[c], zb[c]);
-                    zq[c] = fmaf(-bk, yb[c], zq[c]);
-                } else {
-                    zb[c] += yb[c];   // Z_{-1} is Z_0
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < P; ++c) {
-                za[c] = zb[c];
-                zb[c] = zq[c];
-                zq[c] = 0.f;
-            }
-        }
+    }
+    if (valid)
         for (int c = 0; c < p; ++c) {
             a.Z0bar[r * a.z_rs + c * a.z_cs] = za[c];
             a.Bbar[r * a.b_rs + c * a.b_cs] = bb[c];
         }
-        lbar /= Ld;
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        const int e = lane + j * kAdjRows;
+        if (e < p * p) a.Wpart[(int64_t)blockIdx.x * p * p + e] = wacc[j];
     }
-    lbar = wave_sum(lbar);
-    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = lbar;
-    __syncthreads();
-    if (threadIdx.x == 0) a.Lpart[blockIdx.x] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
+    lbar = wave_sum(lbar / Ld);
+    if (lane == 0) a.Lpart[blockIdx.x] = lbar;
 }
 
-// Wbar[d][c] = -(1/L) sum_s Ys[s][d] Vb[s][c] + Lbar v_d v_c, Lbar = sum of
-// the partials; one wavefront per entry.
-__global__ __launch_bounds__(kThreads) void k_wbar(int p, int64_t S, const float* Ys,
-                                                  const float* Vb, const double* Lp,
-                                                  const double* Lpart, int nparts,
-                                                  const float* v, float* Wbar) {
-    const int lane = threadIdx.x & 63;
-    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (e >= p * p) return;
-    const int d = e / p, c = e % p;
-    double s = 0.0;
-    for (int64_t k = lane; k < S; k += 64) s += (double)Ys[k * p + d] * (double)Vb[k * p + c];
-    s = wave_sum(s);
-    double lb = 0.0;
-    for (int k = lane; k < nparts; k += 64) lb += Lpart[k];
-    lb = wave_sum(lb);
-    if (lane == 0) Wbar[e] = (float)(-s / *Lp + lb * (double)v[d] * (double)v[c]);
+// Wbar[d][c] = -(1/L) sum_b Wpart[b][d][c] + Lbar v_d v_c, Lbar = sum of the
+// Lpart; both sums in workgroup order.
+__global__ __launch_bounds__(kThreads) void k_wbar(int p, const double* Wpart, const double* Lpart,
+                                                  int nparts, const double* Lp, const float* v,
+                                                  float* Wbar) {
+    __shared__ double slb;
+    if (threadIdx.x < 64) {
+        double lb = 0.0;
+        for (int k = threadIdx.x; k < nparts; k += 64) lb += Lpart[k];
+        lb = wave_sum(lb);
+        if (threadIdx.x == 0) slb = lb;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < p * p; e += kThreads) {
+        const int d = e / p, c = e % p;
+        double s = 0.0;
+        for (int b = 0; b < nparts; ++b) s += Wpart[(int64_t)b * p * p + e];
+        Wbar[e] = (float)(-s / *Lp + slb * (double)v[d] * (double)v[c]);
+    }
 }
 
 // dX (n x m, ldd) = U V^T with U n x r, V m x r (row-major): 64 x 64 tiles,
@@ -415,17 +416,18 @@ struct cnmf_tape {
     // checkpoints and segment recompute
     std::vector<float*> Gc, Fc;                 // (G, F) at t = 0, ck, 2 ck, ...
     float *Gh = nullptr, *Fh = nullptr;         // ck x n x p, ck x p x m
+    float* Wh = nullptr;                        // ck x 2 x p x p: each subproblem's W
+    double* Lh = nullptr;                       // ck x 2: each subproblem's L
     int32_t* replay = nullptr;                  // T x 2, all K
     int32_t* rep = nullptr;                     // 4q x 32 replaced-column flags of the RSI
     float* part = nullptr;                      // sweep partials
     // reverse work buffers
     float *Gb = nullptr, *Fb = nullptr, *Gb2 = nullptr, *Fb2 = nullptr;
     float *XRb = nullptr, *XLb = nullptr, *QLb = nullptr, *QRb = nullptr;
-    float *GL = nullptr, *FR = nullptr, *W = nullptr, *Bsub = nullptr, *Bb = nullptr, *Wb = nullptr;
+    float *GL = nullptr, *FR = nullptr, *Bsub = nullptr, *Bb = nullptr, *Wb = nullptr;
     float *GLb = nullptr, *FRb = nullptr, *v = nullptr;
-    double* L = nullptr;
-    float *Zs = nullptr, *Ys = nullptr, *Vb = nullptr;
-    double* Lpart = nullptr;
+    float* Zs = nullptr;
+    double *Wpart = nullptr, *Lpart = nullptr;
     float *U = nullptr, *V = nullptr;           // n x r, m x r
     float *Tn = nullptr, *Tm = nullptr, *Tn2 = nullptr, *Tm2 = nullptr;   // panel temporaries
     float *Rl = nullptr, *Ril = nullptr, *Ml = nullptr, *Cl = nullptr;   // l x l
@@ -543,7 +545,7 @@ int rsi_forward(cnmf_tape* t) {
 }
 
 // Outer iterations [t0, t0 + cnt) from (G, F) in place; with hist, every
-// iterate is kept (segment recompute).
+// iterate and every subproblem's W and L are kept (segment recompute).
 int solve_span(cnmf_tape* t, float* G, float* F, int t0, int cnt, bool hist) {
     cnmf_params prm;
     cnmf_params_default(&prm);
@@ -557,6 +559,8 @@ int solve_span(cnmf_tape* t, float* G, float* F, int t0, int cnt, bool hist) {
     if (hist) {
         tr.G_hist = t->Gh;
         tr.F_hist = t->Fh;
+        tr.W_hist = t->Wh;
+        tr.lips = t->Lh;
     }
     return cnmf_solve(t->c, CNMF_METHOD_COMPRESSED, t->n, t->m, nullptr, 0, t->QLo, t->QRo, t->XL,
                       t->XR, &prm, G, F, hist ? &tr : nullptr, t->replay + 2 * t0);
@@ -564,12 +568,13 @@ int solve_span(cnmf_tape* t, float* G, float* F, int t0, int cnt, bool hist) {
 
 // Reverse of one subproblem: Zbar (adjoint of its output) -> Z0bar, and the
 // adjoints of its W, B and L folded into Wb (p x p) and Bb (strided like B).
-int subproblem_adj(cnmf_tape* t, const Dev& d, int64_t rows, const float* Z0, int64_t z_rs,
-                   int64_t z_cs, const float* B, int64_t b_rs, int64_t b_cs, const float* Zbar,
-                   float* Z0bar) {
+// W and L are the ones the forward solve used (kept by the recompute).
+int subproblem_adj(cnmf_tape* t, const Dev& d, int64_t rows, const float* W, const double* L,
+                   const float* Z0, int64_t z_rs, int64_t z_cs, const float* B, int64_t b_rs,
+                   int64_t b_cs, const float* Zbar, float* Z0bar) {
     const int p = t->p;
-    CK(lipschitz(d, p, t->W, t->L, t->c->ctl));
-    hipLaunchKernelGGL(k_eigvec, dim3(1), dim3(64), 0, d.stream, p, t->W, t->L, t->v);
+    if (p <= 16) hipLaunchKernelGGL(k_eigvec<16>, dim3(1), dim3(64), 0, d.stream, p, W, L, t->v);
+    else hipLaunchKernelGGL(k_eigvec<32>, dim3(1), dim3(64), 0, d.stream, p, W, L, t->v);
     CK(hipGetLastError());
     AdjNnls a{};
     a.rows = rows;
@@ -578,17 +583,17 @@ int subproblem_adj(cnmf_tape* t, const Dev& d, int64_t rows, const float* Z0, in
     a.Z0 = Z0;
     a.z_rs = z_rs;
     a.z_cs = z_cs;
-    a.W = t->W;
+    a.W = W;
     a.B = B;
     a.b_rs = b_rs;
     a.b_cs = b_cs;
-    a.L = t->L;
+    a.L = L;
     a.Zbar = Zbar;
     a.Z0bar = Z0bar;
     a.Bbar = t->Bb;
     a.Zs = t->Zs;
-    a.Ys = t->Ys;
-    a.Vb = t->Vb;
+    a.zs_rows = (int64_t)nb(rows, kAdjRows) * kAdjRows;
+    a.Wpart = t->Wpart;
     a.Lpart = t->Lpart;
     // momentum weights of the forward kernel (the same table): step k uses beta[k]
     {
@@ -597,28 +602,31 @@ int subproblem_adj(cnmf_tape* t, const Dev& d, int64_t rows, const float* Z0, in
         a.beta[0] = 0.f;
         for (int k = 1; k <= t->K; ++k) a.beta[k] = tab[k - 1];
     }
-    const unsigned blocks = nb(rows, kThreads);
-    if (p <= 16) hipLaunchKernelGGL(k_nnls_adj<16>, dim3(blocks), dim3(kThreads), 0, d.stream, a);
-    else hipLaunchKernelGGL(k_nnls_adj<32>, dim3(blocks), dim3(kThreads), 0, d.stream, a);
+    // one wavefront per workgroup: the rows' serial chains spread over many
+    // compute units instead of sharing four per unit
+    const unsigned blocks = nb(rows, kAdjRows);
+    if (p <= 16) hipLaunchKernelGGL(k_nnls_adj<16>, dim3(blocks), dim3(kAdjRows), 0, d.stream, a);
+    else hipLaunchKernelGGL(k_nnls_adj<32>, dim3(blocks), dim3(kAdjRows), 0, d.stream, a);
     CK(hipGetLastError());
-    hipLaunchKernelGGL(k_wbar, dim3(nb(p * p, 4)), dim3(kThreads), 0, d.stream, p,
-                       (int64_t)t->K * rows, t->Ys, t->Vb, t->L, t->Lpart, (int)blocks, t->v,
-                       t->Wb);
+    hipLaunchKernelGGL(k_wbar, dim3(1), dim3(kThreads), 0, d.stream, p, t->Wpart, t->Lpart,
+                       (int)blocks, L, t->v, t->Wb);
     CK(hipGetLastError());
     return CNMF_OK;
 }
 
-// Reverse of outer iteration t: (Gb, Fb) hold dL/dG_t, dL/dF_t on entry and
-// dL/dG_{t-1}, dL/dF_{t-1} on exit; the compressed-data adjoints accumulate.
-int outer_adj(cnmf_tape* t, const float* Gprev, const float* Fprev, const float* Gcur) {
+// Reverse of outer iteration t (entry j of the recomputed segment): (Gb, Fb)
+// hold dL/dG_t, dL/dF_t on entry and dL/dG_{t-1}, dL/dF_{t-1} on exit; the
+// compressed-data adjoints accumulate.
+int outer_adj(cnmf_tape* t, int j, const float* Gprev, const float* Fprev, const float* Gcur) {
     const Dev& d = t->c->dev;
     const int64_t n = t->n, m = t->m;
     const int p = t->p, l = t->l;
     // ---- F update: F_t = NNLS(F_{t-1}; W = G_L^T G_L, B = G_L^T X_L), G_L = Q_L^T G_t
     CK(gemm(d, l, p, n, 1.f, t->QLo, l, true, Gcur, p, false, 0.f, t->GL, p));
-    CK(gemm(d, p, p, l, 1.f, t->GL, p, true, t->GL, p, false, 0.f, t->W, p));
     CK(gemm(d, p, m, l, 1.f, t->GL, p, true, t->XL, m, false, 0.f, t->Bsub, m));
-    int rc = subproblem_adj(t, d, m, Fprev, 1, m, t->Bsub, 1, m, t->Fb, t->Fb2);
+    const size_t pp = (size_t)p * p;
+    int rc = subproblem_adj(t, d, m, t->Wh + (2 * j + 1) * pp, t->Lh + 2 * j + 1, Fprev, 1, m,
+                            t->Bsub, 1, m, t->Fb, t->Fb2);
     if (rc) return rc;
     // G_L bar = G_L (Wb + Wb^T) + X_L Bb^T ; X_L bar += G_L Bb
     CK(gemm(d, l, p, p, 1.f, t->GL, p, false, t->Wb, p, false, 0.f, t->GLb, p));
@@ -630,9 +638,9 @@ int outer_adj(cnmf_tape* t, const float* Gprev, const float* Fprev, const float*
     CK(gemm(d, n, l, p, 1.f, Gcur, p, false, t->GLb, p, true, 1.f, t->QLb, l));
     // ---- G update: G_t = NNLS(G_{t-1}; W = F_R F_R^T, B = X_R F_R^T), F_R = F_{t-1} Q_R
     CK(gemm(d, p, l, m, 1.f, Fprev, m, false, t->QRo, l, false, 0.f, t->FR, l));
-    CK(gemm(d, p, p, l, 1.f, t->FR, l, false, t->FR, l, true, 0.f, t->W, p));
     CK(gemm(d, n, p, l, 1.f, t->XR, l, false, t->FR, l, true, 0.f, t->Bsub, p));
-    rc = subproblem_adj(t, d, n, Gprev, p, 1, t->Bsub, p, 1, t->Gb, t->Gb2);
+    rc = subproblem_adj(t, d, n, t->Wh + 2 * j * pp, t->Lh + 2 * j, Gprev, p, 1, t->Bsub, p, 1,
+                        t->Gb, t->Gb2);
     if (rc) return rc;
     // F_R bar = (Wb + Wb^T) F_R + Bb^T X_R ; X_R bar += Bb F_R
     CK(gemm(d, p, l, p, 1.f, t->Wb, p, false, t->FR, l, false, 0.f, t->FRb, l));
@@ -760,6 +768,8 @@ int cnmf_adj_forward(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t 
     for (int k = 0; k < nck; ++k) { take((size_t)n * p); take((size_t)p * m); }   // checkpoints
     take((size_t)ckpt * n * p);
     take((size_t)ckpt * p * m);
+    take((size_t)ckpt * 2 * p * p);                                            // Wh
+    const size_t o_lh = ar.take<double>((size_t)ckpt * 2);
     const size_t o_rep = ar.take<int32_t>((size_t)2 * T);
     const size_t o_flags = ar.take<int32_t>((size_t)4 * q * 32);
     const size_t pf = std::max(sweep_right_partial_floats(c->dev, n, m),
@@ -768,14 +778,14 @@ int cnmf_adj_forward(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t 
     const size_t base_work = o.size();
     take((size_t)n * p); take((size_t)p * m); take((size_t)n * p); take((size_t)p * m);   // Gb Fb Gb2 Fb2
     take(NL); take((size_t)l * m); take(NL); take(ML);                         // XRb XLb QLb QRb
-    take((size_t)l * p); take((size_t)p * l); take((size_t)p * p);             // GL FR W
+    take((size_t)l * p); take((size_t)p * l);                                  // GL FR
     const int64_t nm = std::max(n, m);
     take((size_t)nm * p); take((size_t)nm * p); take((size_t)p * p);           // Bsub Bb Wb
     take((size_t)l * p); take((size_t)p * l); take(32);                        // GLb FRb v
-    const size_t o_L = ar.take<double>(1);
-    take((size_t)(kMaxK + 1) * nm * 32);                                       // Zs
-    take((size_t)kMaxK * nm * p); take((size_t)kMaxK * nm * p);               // Ys Vb
-    const size_t o_lp = ar.take<double>(nb(nm, kThreads));
+    const size_t nm_pad = (size_t)nb(nm, kAdjRows) * kAdjRows;
+    take((size_t)(kMaxK + 1) * nm_pad * 32);                                   // Zs
+    const size_t o_wp = ar.take<double>((size_t)nb(nm, kAdjRows) * p * p);
+    const size_t o_lp = ar.take<double>(nb(nm, kAdjRows));
     take((size_t)n * r); take((size_t)m * r);                                  // U V
     take(NL); take(ML); take(NL); take(ML);                                    // Tn Tm Tn2 Tm2
     take((size_t)l * l); take((size_t)l * l); take((size_t)l * l); take((size_t)l * l);
@@ -799,18 +809,19 @@ int cnmf_adj_forward(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t 
     for (int k = 0; k < nck; ++k) { t->Gc.push_back(F(i++)); t->Fc.push_back(F(i++)); }
     t->Gh = F(i++);
     t->Fh = F(i++);
+    t->Wh = F(i++);
+    t->Lh = reinterpret_cast<double*>(t->mem + o_lh);
     t->replay = reinterpret_cast<int32_t*>(t->mem + o_rep);
     t->rep = reinterpret_cast<int32_t*>(t->mem + o_flags);
     t->part = F(i++);
     if (i != base_work) { cnmf_tape_destroy(t); return CNMF_EINVAL; }
     t->Gb = F(i++); t->Fb = F(i++); t->Gb2 = F(i++); t->Fb2 = F(i++);
     t->XRb = F(i++); t->XLb = F(i++); t->QLb = F(i++); t->QRb = F(i++);
-    t->GL = F(i++); t->FR = F(i++); t->W = F(i++);
+    t->GL = F(i++); t->FR = F(i++);
     t->Bsub = F(i++); t->Bb = F(i++); t->Wb = F(i++);
     t->GLb = F(i++); t->FRb = F(i++); t->v = F(i++);
-    t->L = reinterpret_cast<double*>(t->mem + o_L);
     t->Zs = F(i++);
-    t->Ys = F(i++); t->Vb = F(i++);
+    t->Wpart = reinterpret_cast<double*>(t->mem + o_wp);
     t->Lpart = reinterpret_cast<double*>(t->mem + o_lp);
     t->U = F(i++); t->V = F(i++);
     t->Tn = F(i++); t->Tm = F(i++); t->Tn2 = F(i++); t->Tm2 = F(i++);
@@ -881,7 +892,7 @@ int cnmf_adj_backward(cnmf_tape* t, const float* dG, const float* dF, float* dX,
             const float* Gcur = t->Gh + (size_t)j * n * p;
             const float* Gprev = j > 0 ? t->Gh + (size_t)(j - 1) * n * p : t->Gc[s];
             const float* Fprev = j > 0 ? t->Fh + (size_t)(j - 1) * p * m : t->Fc[s];
-            rc = outer_adj(t, Gprev, Fprev, Gcur);
+            rc = outer_adj(t, j, Gprev, Fprev, Gcur);
             if (rc) return rc;
         }
     }
