@@ -13,6 +13,7 @@
 // dL/dX = sum_j U_j V_j^T over 2(2q+1) rank-l pairs, formed by one final
 // U V^T product.
 #include <cmath>
+#include <initializer_list>
 #include <vector>
 
 #include "ctx.hpp"
@@ -64,6 +65,75 @@ __global__ __launch_bounds__(kThreads) void k_gemm_long(int64_t M, int64_t N, in
         const float old = beta != 0.f ? C[i * ldc + j] : 0.f;
         C[i * ldc + j] = alpha * s + beta * old;
     }
+}
+
+// Up to two independent outputs per launch, each a sum of up to three
+// products: C = sum_t alpha_t op(A_t) op(B_t) + beta C.  An output with a
+// long reduction (any K > 64) takes one wavefront per entry, otherwise one
+// lane per entry; the waves of output 0 come first.
+struct MTerm {
+    const float* A;
+    const float* B;
+    int64_t lda, ldb, K;
+    int ta, tb;
+    float alpha;
+};
+struct MOut {
+    float* C;
+    int64_t M, N, ldc;
+    float beta;
+    int nterm, wide;
+    MTerm term[3];
+};
+struct MGemm {
+    MOut out[2];
+    int64_t first1, waves;   // first wave of output 1, total waves
+};
+
+__device__ __forceinline__ void mgemm_out(const MOut& u, int64_t w, int lane) {
+    if (u.wide) {
+        const int64_t i = w / u.N, j = w - i * u.N;
+        float s = 0.f;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            if (t >= u.nterm) break;
+            const MTerm& m = u.term[t];
+            float acc = 0.f;
+#pragma unroll 8
+            for (int64_t k = lane; k < m.K; k += 64)
+                acc = fmaf(opA(m.A, m.lda, m.ta, i, k), opB(m.B, m.ldb, m.tb, k, j), acc);
+            s = fmaf(m.alpha, wave_sum(acc), s);
+        }
+        if (lane == 0) {
+            const float old = u.beta != 0.f ? u.C[i * u.ldc + j] : 0.f;
+            u.C[i * u.ldc + j] = fmaf(u.beta, old, s);
+        }
+    } else {
+        const int64_t e = w * 64 + lane;
+        if (e >= u.M * u.N) return;
+        const int64_t i = e / u.N, j = e - i * u.N;
+        float s = 0.f;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            if (t >= u.nterm) break;
+            const MTerm& m = u.term[t];
+            float acc = 0.f;
+#pragma unroll 8
+            for (int64_t k = 0; k < m.K; ++k)
+                acc = fmaf(opA(m.A, m.lda, m.ta, i, k), opB(m.B, m.ldb, m.tb, k, j), acc);
+            s = fmaf(m.alpha, acc, s);
+        }
+        const float old = u.beta != 0.f ? u.C[i * u.ldc + j] : 0.f;
+        u.C[i * u.ldc + j] = fmaf(u.beta, old, s);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_mgemm(MGemm g) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= g.waves) return;   // uniform per wave
+    if (w < g.first1) mgemm_out(g.out[0], w, lane);
+    else mgemm_out(g.out[1], w - g.first1, lane);
 }
 
 __global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, float alpha, const float* x, float* y) {
@@ -120,9 +190,12 @@ __global__ __launch_bounds__(64) void k_tri_inv(int l, const float* R, float* Ri
 // read from lane k.  The sign is fixed so that the largest component is
 // positive.
 template <int P>
-__global__ __launch_bounds__(64) void k_eigvec(int p, const float* W, const double* Lp, float* v) {
+__global__ __launch_bounds__(64) void k_eigvec(int p, const float* Ws, const double* Ls, float* vs) {
+    // workgroup b: W = Ws + b p^2, L = Ls[b], v = vs + 32 b
+    const float* W = Ws + (int64_t)blockIdx.x * p * p;
+    float* v = vs + (int64_t)blockIdx.x * 32;
     const int lane = threadIdx.x;
-    const double L = *Lp;
+    const double L = Ls[blockIdx.x];
     const double sigma = L * (1.0 + 1e-9) + 1e-300;
     double x = lane < p ? 1.0 / sqrt((double)p) : 0.0;
     for (int it = 0; it < 2; ++it) {
@@ -177,7 +250,7 @@ __global__ __launch_bounds__(64) void k_eigvec(int p, const float* W, const doub
 // ---------------------------------------------------------------------------
 constexpr int kAdjRows = 64;   // rows (lanes) per workgroup of the NNLS reverse
 struct AdjNnls {
-    int64_t rows, zs_rows;   // zs_rows: rows of the Zs tape (a multiple of kAdjRows)
+    int64_t rows;
     int p, K;
     const float* Z0;
     int64_t z_rs, z_cs;
@@ -188,25 +261,58 @@ struct AdjNnls {
     const float* Zbar;
     float* Z0bar;            // same strides as Z0
     float* Bbar;             // same strides as B
-    float* Zs;               // [K + 1][zs_rows][32]
     double* Wpart;           // [gridDim.x][p][p]
     double* Lpart;           // [gridDim.x]
+    float* Zs;               // P = 32: [K + 1][gridDim.x * kAdjRows][32] (HBM tape)
     float beta[kMaxK + 1];   // beta[k] = b_k, k = 1..K
 };
+
+// The iterates Z_0 .. Z_K of the workgroup's rows stay in LDS for P = 16
+// (dynamic LDS of the bytes below, at most 40 KB) and go to an HBM tape for
+// P = 32, where they would not fit beside the other arrays in 64 KB.
+constexpr bool adj_lds_tape(int P) { return P <= 16; }
+constexpr size_t adj_lds_bytes(int P, int K) {
+    return adj_lds_tape(P) ? (size_t)(K + 1) * kAdjRows * (P + 1) * 4 : 0;
+}
+
+// g = y W - b for one row (W zero-padded to P x P in LDS, read as float4)
+template <int P>
+__device__ __forceinline__ void row_times_w(const float (&y)[P], const float (*sW)[P], float (&g)[P]) {
+#pragma unroll
+    for (int d = 0; d < P; ++d) {
+        const float4* w4 = reinterpret_cast<const float4*>(sW[d]);
+#pragma unroll
+        for (int c4 = 0; c4 < P / 4; ++c4) {
+            const float4 w = w4[c4];
+            g[4 * c4 + 0] = fmaf(y[d], w.x, g[4 * c4 + 0]);
+            g[4 * c4 + 1] = fmaf(y[d], w.y, g[4 * c4 + 1]);
+            g[4 * c4 + 2] = fmaf(y[d], w.z, g[4 * c4 + 2]);
+            g[4 * c4 + 3] = fmaf(y[d], w.w, g[4 * c4 + 3]);
+        }
+    }
+}
 
 template <int P>
 __global__ __launch_bounds__(kAdjRows) void k_nnls_adj(AdjNnls a) {
     constexpr int NE = (P * P + kAdjRows - 1) / kAdjRows;   // W entries per lane
-    __shared__ float sW[32][33];
+    __shared__ __align__(16) float sW[P][P];
     __shared__ float sy[kAdjRows][P + 1], sv[kAdjRows][P + 1];
+    extern __shared__ float zt[];   // [K + 1][kAdjRows][P + 1]
     const int p = a.p;
     const int lane = threadIdx.x;
-    for (int e = lane; e < p * p; e += kAdjRows) sW[e / p][e % p] = a.W[e];
+    for (int e = lane; e < P * P; e += kAdjRows) {
+        const int d = e / P, c = e % P;
+        sW[d][c] = (d < p && c < p) ? a.W[d * p + c] : 0.f;
+    }
     __syncthreads();
     const double Ld = *a.L;
     const float invL = (float)(1.0 / Ld);
     const int64_t r = (int64_t)blockIdx.x * kAdjRows + lane;
     const bool valid = r < a.rows;
+    auto zs = [&](int k) -> float* {
+        if constexpr (adj_lds_tape(P)) return zt + ((size_t)k * kAdjRows + lane) * (P + 1);
+        else return a.Zs + ((int64_t)k * gridDim.x * kAdjRows + r) * 32;
+    };
     // rows past the end run on zeros: every product below is then zero
     float b[P], zc[P], zp[P];
 #pragma unroll
@@ -215,28 +321,24 @@ __global__ __launch_bounds__(kAdjRows) void k_nnls_adj(AdjNnls a) {
         zc[c] = (valid && c < p) ? a.Z0[r * a.z_rs + c * a.z_cs] : 0.f;
         zp[c] = zc[c];
     }
-    auto zs = [&](int k) { return a.Zs + ((int64_t)k * a.zs_rows + r) * 32; };
 #pragma unroll
     for (int c = 0; c < P; ++c) zs(0)[c] = zc[c];
     // forward recompute, keeping Z_0 .. Z_K
     for (int k = 1; k <= a.K; ++k) {
         const float bk = a.beta[k];
-        float y[P], zn[P];
-#pragma unroll
-        for (int c = 0; c < P; ++c) y[c] = fmaf(bk, zc[c] - zp[c], zc[c]);
+        float y[P], g[P];
 #pragma unroll
         for (int c = 0; c < P; ++c) {
-            float g = -b[c];
-#pragma unroll
-            for (int d = 0; d < P; ++d) g = fmaf(y[d], d < p && c < p ? sW[d][c] : 0.f, g);
-            const float v = fmaf(-g, invL, y[c]);
-            zn[c] = (v > 0.f || v != v) ? v : 0.f;
+            y[c] = fmaf(bk, zc[c] - zp[c], zc[c]);
+            g[c] = -b[c];
         }
+        row_times_w<P>(y, sW, g);
 #pragma unroll
         for (int c = 0; c < P; ++c) {
+            const float v = fmaf(-g[c], invL, y[c]);
             zp[c] = zc[c];
-            zc[c] = zn[c];
-            zs(k)[c] = zn[c];
+            zc[c] = (v > 0.f || v != v) ? v : 0.f;
+            zs(k)[c] = zc[c];
         }
     }
     // reverse: za = dL/dZ_k (complete), zb = dL/dZ_{k-1}, zq = dL/dZ_{k-2}
@@ -256,15 +358,16 @@ __global__ __launch_bounds__(kAdjRows) void k_nnls_adj(AdjNnls a) {
         const float bk = a.beta[k];
         const float* z1 = zs(k - 1);
         const float* z2 = zs(k >= 2 ? k - 2 : 0);
-        float y[P], vb[P];
-#pragma unroll
-        for (int c = 0; c < P; ++c) y[c] = fmaf(bk, z1[c] - z2[c], z1[c]);
+        float y[P], g[P], vb[P];
 #pragma unroll
         for (int c = 0; c < P; ++c) {
-            float g = -b[c];
+            y[c] = fmaf(bk, z1[c] - z2[c], z1[c]);
+            g[c] = -b[c];
+        }
+        row_times_w<P>(y, sW, g);
 #pragma unroll
-            for (int d = 0; d < P; ++d) g = fmaf(y[d], d < p && c < p ? sW[d][c] : 0.f, g);
-            const float v = fmaf(-g, invL, y[c]);
+        for (int c = 0; c < P; ++c) {
+            const float v = fmaf(-g[c], invL, y[c]);
             vb[c] = (v > 0.f) ? za[c] : 0.f;
             lbar += (double)vb[c] * (double)(y[c] - v);
         }
@@ -286,23 +389,21 @@ __global__ __launch_bounds__(kAdjRows) void k_nnls_adj(AdjNnls a) {
                 wacc[j] += s;
             }
         }
-        // ybar = vbar (I - W / L)^T, with V = Y (I - W/L) + b / L
-        float yb[P];
+        // ybar = vbar (I - W / L)^T, with V = Y (I - W/L) + b / L; W is
+        // symmetric, so vbar W^T = vbar W
+        float s[P];
 #pragma unroll
-        for (int d = 0; d < P; ++d) {
-            float s = 0.f;
-#pragma unroll
-            for (int c = 0; c < P; ++c) s = fmaf(vb[c], d < p && c < p ? sW[d][c] : 0.f, s);
-            yb[d] = fmaf(-s, invL, vb[d]);
-        }
+        for (int c = 0; c < P; ++c) s[c] = 0.f;
+        row_times_w<P>(vb, sW, s);
 #pragma unroll
         for (int c = 0; c < P; ++c) {
+            const float yb = fmaf(-s[c], invL, vb[c]);
             bb[c] = fmaf(vb[c], invL, bb[c]);
             if (k >= 2) {
-                zb[c] = fmaf(1.f + bk, yb[c], zb[c]);
-                zq[c] = fmaf(-bk, yb[c], zq[c]);
+                zb[c] = fmaf(1.f + bk, yb, zb[c]);
+                zq[c] = fmaf(-bk, yb, zq[c]);
             } else {
-                zb[c] += yb[c];   // Z_{-1} is Z_0
+                zb[c] += yb;   // Z_{-1} is Z_0
             }
         }
 #pragma unroll
@@ -326,12 +427,14 @@ __global__ __launch_bounds__(kAdjRows) void k_nnls_adj(AdjNnls a) {
     if (lane == 0) a.Lpart[blockIdx.x] = lbar;
 }
 
-// Wbar[d][c] = -(1/L) sum_b Wpart[b][d][c] + Lbar v_d v_c, Lbar = sum of the
-// Lpart; both sums in workgroup order.
+// Wbs = Wbar + Wbar^T with Wbar[d][c] = -(1/L) sum_b Wpart[b][d][c] +
+// Lbar v_d v_c, Lbar = sum of the Lpart; both sums in workgroup order (the
+// partials of eight workgroups loaded together).
 __global__ __launch_bounds__(kThreads) void k_wbar(int p, const double* Wpart, const double* Lpart,
                                                   int nparts, const double* Lp, const float* v,
-                                                  float* Wbar) {
+                                                  float* Wbs) {
     __shared__ double slb;
+    __shared__ float sw[32][33];
     if (threadIdx.x < 64) {
         double lb = 0.0;
         for (int k = threadIdx.x; k < nparts; k += 64) lb += Lpart[k];
@@ -339,11 +442,25 @@ __global__ __launch_bounds__(kThreads) void k_wbar(int p, const double* Wpart, c
         if (threadIdx.x == 0) slb = lb;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < p * p; e += kThreads) {
+    const int64_t pp = (int64_t)p * p;
+    for (int e = threadIdx.x; e < pp; e += kThreads) {
         const int d = e / p, c = e % p;
         double s = 0.0;
-        for (int b = 0; b < nparts; ++b) s += Wpart[(int64_t)b * p * p + e];
-        Wbar[e] = (float)(-s / *Lp + slb * (double)v[d] * (double)v[c]);
+        int b = 0;
+        for (; b + 8 <= nparts; b += 8) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = Wpart[(b + u) * pp + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += t[u];
+        }
+        for (; b < nparts; ++b) s += Wpart[b * pp + e];
+        sw[d][c] = (float)(-s / *Lp + slb * (double)v[d] * (double)v[c]);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < pp; e += kThreads) {
+        const int d = e / p, c = e % p;
+        Wbs[e] = sw[d][c] + sw[c][d];
     }
 }
 
@@ -417,6 +534,7 @@ struct cnmf_tape {
     std::vector<float*> Gc, Fc;                 // (G, F) at t = 0, ck, 2 ck, ...
     float *Gh = nullptr, *Fh = nullptr;         // ck x n x p, ck x p x m
     float* Wh = nullptr;                        // ck x 2 x p x p: each subproblem's W
+    float* Vh = nullptr;                        // ck x 2 x 32: its top eigenvector
     double* Lh = nullptr;                       // ck x 2: each subproblem's L
     int32_t* replay = nullptr;                  // T x 2, all K
     int32_t* rep = nullptr;                     // 4q x 32 replaced-column flags of the RSI
@@ -424,10 +542,10 @@ struct cnmf_tape {
     // reverse work buffers
     float *Gb = nullptr, *Fb = nullptr, *Gb2 = nullptr, *Fb2 = nullptr;
     float *XRb = nullptr, *XLb = nullptr, *QLb = nullptr, *QRb = nullptr;
-    float *GL = nullptr, *FR = nullptr, *Bsub = nullptr, *Bb = nullptr, *Wb = nullptr;
-    float *GLb = nullptr, *FRb = nullptr, *v = nullptr;
-    float* Zs = nullptr;
+    float *GL = nullptr, *FR = nullptr, *Bsub = nullptr, *Bsub2 = nullptr, *Bb = nullptr, *Wb = nullptr;
+    float *GLb = nullptr, *FRb = nullptr;
     double *Wpart = nullptr, *Lpart = nullptr;
+    float* Zs = nullptr;                        // p > 16: HBM tape of the NNLS reverse
     float *U = nullptr, *V = nullptr;           // n x r, m x r
     float *Tn = nullptr, *Tm = nullptr, *Tn2 = nullptr, *Tm2 = nullptr;   // panel temporaries
     float *Rl = nullptr, *Ril = nullptr, *Ml = nullptr, *Cl = nullptr;   // l x l
@@ -446,6 +564,48 @@ hipError_t gemm(const Dev& d, int64_t M, int64_t N, int64_t K, float alpha, cons
     else
         hipLaunchKernelGGL(k_gemm_short, dim3(nb(M * N, kThreads)), dim3(kThreads), 0, d.stream, M,
                            N, K, alpha, A, lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, beta, C, ldc);
+    return hipGetLastError();
+}
+
+MTerm term(const float* A, int64_t lda, bool ta, const float* B, int64_t ldb, bool tb, int64_t K,
+           float alpha = 1.f) {
+    MTerm m{};
+    m.A = A;
+    m.B = B;
+    m.lda = lda;
+    m.ldb = ldb;
+    m.K = K;
+    m.ta = ta ? 1 : 0;
+    m.tb = tb ? 1 : 0;
+    m.alpha = alpha;
+    return m;
+}
+
+MOut out(float* C, int64_t M, int64_t N, int64_t ldc, float beta, std::initializer_list<MTerm> ts) {
+    MOut o{};
+    o.C = C;
+    o.M = M;
+    o.N = N;
+    o.ldc = ldc;
+    o.beta = beta;
+    for (const MTerm& m : ts) {
+        o.term[o.nterm++] = m;
+        if (m.K > 64) o.wide = 1;
+    }
+    return o;
+}
+
+int64_t out_waves(const MOut& o) { return o.wide ? o.M * o.N : (o.M * o.N + 63) / 64; }
+
+// o0 and o1 in one launch (independent outputs)
+hipError_t mgemm(const Dev& d, const MOut& o0, const MOut& o1) {
+    MGemm g{};
+    g.out[0] = o0;
+    g.out[1] = o1;
+    g.first1 = out_waves(o0);
+    g.waves = g.first1 + out_waves(o1);
+    if (g.waves <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mgemm, dim3(nb(g.waves, 4)), dim3(kThreads), 0, d.stream, g);
     return hipGetLastError();
 }
 
@@ -567,15 +727,13 @@ int solve_span(cnmf_tape* t, float* G, float* F, int t0, int cnt, bool hist) {
 }
 
 // Reverse of one subproblem: Zbar (adjoint of its output) -> Z0bar, and the
-// adjoints of its W, B and L folded into Wb (p x p) and Bb (strided like B).
-// W and L are the ones the forward solve used (kept by the recompute).
+// adjoints of its W, B and L folded into Wb (p x p, W's adjoint plus its
+// transpose) and Bb (strided like B).  W, L and the top eigenvector v are
+// the forward's (kept by the recompute).
 int subproblem_adj(cnmf_tape* t, const Dev& d, int64_t rows, const float* W, const double* L,
-                   const float* Z0, int64_t z_rs, int64_t z_cs, const float* B, int64_t b_rs,
-                   int64_t b_cs, const float* Zbar, float* Z0bar) {
+                   const float* v, const float* Z0, int64_t z_rs, int64_t z_cs, const float* B,
+                   int64_t b_rs, int64_t b_cs, const float* Zbar, float* Z0bar) {
     const int p = t->p;
-    if (p <= 16) hipLaunchKernelGGL(k_eigvec<16>, dim3(1), dim3(64), 0, d.stream, p, W, L, t->v);
-    else hipLaunchKernelGGL(k_eigvec<32>, dim3(1), dim3(64), 0, d.stream, p, W, L, t->v);
-    CK(hipGetLastError());
     AdjNnls a{};
     a.rows = rows;
     a.p = p;
@@ -591,10 +749,9 @@ int subproblem_adj(cnmf_tape* t, const Dev& d, int64_t rows, const float* W, con
     a.Zbar = Zbar;
     a.Z0bar = Z0bar;
     a.Bbar = t->Bb;
-    a.Zs = t->Zs;
-    a.zs_rows = (int64_t)nb(rows, kAdjRows) * kAdjRows;
     a.Wpart = t->Wpart;
     a.Lpart = t->Lpart;
+    a.Zs = t->Zs;
     // momentum weights of the forward kernel (the same table): step k uses beta[k]
     {
         float tab[kMaxK + 1];
@@ -605,51 +762,58 @@ int subproblem_adj(cnmf_tape* t, const Dev& d, int64_t rows, const float* W, con
     // one wavefront per workgroup: the rows' serial chains spread over many
     // compute units instead of sharing four per unit
     const unsigned blocks = nb(rows, kAdjRows);
-    if (p <= 16) hipLaunchKernelGGL(k_nnls_adj<16>, dim3(blocks), dim3(kAdjRows), 0, d.stream, a);
-    else hipLaunchKernelGGL(k_nnls_adj<32>, dim3(blocks), dim3(kAdjRows), 0, d.stream, a);
+    if (p <= 16)
+        hipLaunchKernelGGL(k_nnls_adj<16>, dim3(blocks), dim3(kAdjRows), adj_lds_bytes(16, t->K),
+                           d.stream, a);
+    else
+        hipLaunchKernelGGL(k_nnls_adj<32>, dim3(blocks), dim3(kAdjRows), adj_lds_bytes(32, t->K),
+                           d.stream, a);
     CK(hipGetLastError());
     hipLaunchKernelGGL(k_wbar, dim3(1), dim3(kThreads), 0, d.stream, p, t->Wpart, t->Lpart,
-                       (int)blocks, L, t->v, t->Wb);
+                       (int)blocks, L, v, t->Wb);
     CK(hipGetLastError());
     return CNMF_OK;
 }
 
 // Reverse of outer iteration t (entry j of the recomputed segment): (Gb, Fb)
 // hold dL/dG_t, dL/dF_t on entry and dL/dG_{t-1}, dL/dF_{t-1} on exit; the
-// compressed-data adjoints accumulate.
+// compressed-data adjoints accumulate.  G_t = NNLS(G_{t-1}; F_R F_R^T,
+// X_R F_R^T) with F_R = F_{t-1} Q_R, then F_t = NNLS(F_{t-1}; G_L^T G_L,
+// G_L^T X_L) with G_L = Q_L^T G_t; the F update is reversed first.
 int outer_adj(cnmf_tape* t, int j, const float* Gprev, const float* Fprev, const float* Gcur) {
     const Dev& d = t->c->dev;
     const int64_t n = t->n, m = t->m;
     const int p = t->p, l = t->l;
-    // ---- F update: F_t = NNLS(F_{t-1}; W = G_L^T G_L, B = G_L^T X_L), G_L = Q_L^T G_t
-    CK(gemm(d, l, p, n, 1.f, t->QLo, l, true, Gcur, p, false, 0.f, t->GL, p));
-    CK(gemm(d, p, m, l, 1.f, t->GL, p, true, t->XL, m, false, 0.f, t->Bsub, m));
     const size_t pp = (size_t)p * p;
-    int rc = subproblem_adj(t, d, m, t->Wh + (2 * j + 1) * pp, t->Lh + 2 * j + 1, Fprev, 1, m,
+    const int sG = 2 * j, sF = 2 * j + 1;   // subproblem slots in the kept W, L, v
+    // G_L = Q_L^T G_t (l x p) and F_R = F_{t-1} Q_R (p x l)
+    CK(mgemm(d, out(t->GL, l, p, p, 0.f, {term(t->QLo, l, true, Gcur, p, false, n)}),
+             out(t->FR, p, l, l, 0.f, {term(Fprev, m, false, t->QRo, l, false, m)})));
+    // the subproblems' B: G_L^T X_L (p x m) and X_R F_R^T (n x p)
+    CK(mgemm(d, out(t->Bsub, p, m, m, 0.f, {term(t->GL, p, true, t->XL, m, false, l)}),
+             out(t->Bsub2, n, p, p, 0.f, {term(t->XR, l, false, t->FR, l, true, l)})));
+    // ---- F update
+    int rc = subproblem_adj(t, d, m, t->Wh + sF * pp, t->Lh + sF, t->Vh + 32 * sF, Fprev, 1, m,
                             t->Bsub, 1, m, t->Fb, t->Fb2);
     if (rc) return rc;
-    // G_L bar = G_L (Wb + Wb^T) + X_L Bb^T ; X_L bar += G_L Bb
-    CK(gemm(d, l, p, p, 1.f, t->GL, p, false, t->Wb, p, false, 0.f, t->GLb, p));
-    CK(gemm(d, l, p, p, 1.f, t->GL, p, false, t->Wb, p, true, 1.f, t->GLb, p));
-    CK(gemm(d, l, p, m, 1.f, t->XL, m, false, t->Bb, m, true, 1.f, t->GLb, p));
-    CK(gemm(d, l, m, p, 1.f, t->GL, p, false, t->Bb, m, false, 1.f, t->XLb, m));
+    // G_L bar = G_L Wb + X_L Bb^T ; X_L bar += G_L Bb
+    CK(mgemm(d, out(t->GLb, l, p, p, 0.f, {term(t->GL, p, false, t->Wb, p, false, p),
+                                           term(t->XL, m, false, t->Bb, m, true, m)}),
+             out(t->XLb, l, m, m, 1.f, {term(t->GL, p, false, t->Bb, m, false, p)})));
     // G_t bar += Q_L G_L bar ; Q_L bar += G_t G_L bar^T
-    CK(gemm(d, n, p, l, 1.f, t->QLo, l, false, t->GLb, p, false, 1.f, t->Gb, p));
-    CK(gemm(d, n, l, p, 1.f, Gcur, p, false, t->GLb, p, true, 1.f, t->QLb, l));
-    // ---- G update: G_t = NNLS(G_{t-1}; W = F_R F_R^T, B = X_R F_R^T), F_R = F_{t-1} Q_R
-    CK(gemm(d, p, l, m, 1.f, Fprev, m, false, t->QRo, l, false, 0.f, t->FR, l));
-    CK(gemm(d, n, p, l, 1.f, t->XR, l, false, t->FR, l, true, 0.f, t->Bsub, p));
-    rc = subproblem_adj(t, d, n, t->Wh + 2 * j * pp, t->Lh + 2 * j, Gprev, p, 1, t->Bsub, p, 1,
-                        t->Gb, t->Gb2);
+    CK(mgemm(d, out(t->Gb, n, p, p, 1.f, {term(t->QLo, l, false, t->GLb, p, false, l)}),
+             out(t->QLb, n, l, l, 1.f, {term(Gcur, p, false, t->GLb, p, true, p)})));
+    // ---- G update
+    rc = subproblem_adj(t, d, n, t->Wh + sG * pp, t->Lh + sG, t->Vh + 32 * sG, Gprev, p, 1,
+                        t->Bsub2, p, 1, t->Gb, t->Gb2);
     if (rc) return rc;
-    // F_R bar = (Wb + Wb^T) F_R + Bb^T X_R ; X_R bar += Bb F_R
-    CK(gemm(d, p, l, p, 1.f, t->Wb, p, false, t->FR, l, false, 0.f, t->FRb, l));
-    CK(gemm(d, p, l, p, 1.f, t->Wb, p, true, t->FR, l, false, 1.f, t->FRb, l));
-    CK(gemm(d, p, l, n, 1.f, t->Bb, p, true, t->XR, l, false, 1.f, t->FRb, l));
-    CK(gemm(d, n, l, p, 1.f, t->Bb, p, false, t->FR, l, false, 1.f, t->XRb, l));
+    // F_R bar = Wb F_R + Bb^T X_R ; X_R bar += Bb F_R
+    CK(mgemm(d, out(t->FRb, p, l, l, 0.f, {term(t->Wb, p, false, t->FR, l, false, p),
+                                           term(t->Bb, p, true, t->XR, l, false, n)}),
+             out(t->XRb, n, l, l, 1.f, {term(t->Bb, p, false, t->FR, l, false, p)})));
     // F_{t-1} bar += F_R bar Q_R^T ; Q_R bar += F_{t-1}^T F_R bar
-    CK(gemm(d, p, m, l, 1.f, t->FRb, l, false, t->QRo, l, true, 1.f, t->Fb2, m));
-    CK(gemm(d, m, l, p, 1.f, Fprev, m, true, t->FRb, l, false, 1.f, t->QRb, l));
+    CK(mgemm(d, out(t->Fb2, p, m, m, 1.f, {term(t->FRb, l, false, t->QRo, l, true, l)}),
+             out(t->QRb, m, l, l, 1.f, {term(Fprev, m, true, t->FRb, l, false, p)})));
     std::swap(t->Gb, t->Gb2);
     std::swap(t->Fb, t->Fb2);
     return CNMF_OK;
@@ -769,6 +933,7 @@ int cnmf_adj_forward(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t 
     take((size_t)ckpt * n * p);
     take((size_t)ckpt * p * m);
     take((size_t)ckpt * 2 * p * p);                                            // Wh
+    take((size_t)ckpt * 2 * 32);                                               // Vh
     const size_t o_lh = ar.take<double>((size_t)ckpt * 2);
     const size_t o_rep = ar.take<int32_t>((size_t)2 * T);
     const size_t o_flags = ar.take<int32_t>((size_t)4 * q * 32);
@@ -780,10 +945,10 @@ int cnmf_adj_forward(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t 
     take(NL); take((size_t)l * m); take(NL); take(ML);                         // XRb XLb QLb QRb
     take((size_t)l * p); take((size_t)p * l);                                  // GL FR
     const int64_t nm = std::max(n, m);
-    take((size_t)nm * p); take((size_t)nm * p); take((size_t)p * p);           // Bsub Bb Wb
-    take((size_t)l * p); take((size_t)p * l); take(32);                        // GLb FRb v
+    take((size_t)nm * p); take((size_t)nm * p); take((size_t)nm * p);          // Bsub Bsub2 Bb
+    take((size_t)p * p); take((size_t)l * p); take((size_t)p * l);             // Wb GLb FRb
     const size_t nm_pad = (size_t)nb(nm, kAdjRows) * kAdjRows;
-    take((size_t)(kMaxK + 1) * nm_pad * 32);                                   // Zs
+    take(p > 16 ? (size_t)(kMaxK + 1) * nm_pad * 32 : 1);                      // Zs
     const size_t o_wp = ar.take<double>((size_t)nb(nm, kAdjRows) * p * p);
     const size_t o_lp = ar.take<double>(nb(nm, kAdjRows));
     take((size_t)n * r); take((size_t)m * r);                                  // U V
@@ -810,6 +975,7 @@ int cnmf_adj_forward(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t 
     t->Gh = F(i++);
     t->Fh = F(i++);
     t->Wh = F(i++);
+    t->Vh = F(i++);
     t->Lh = reinterpret_cast<double*>(t->mem + o_lh);
     t->replay = reinterpret_cast<int32_t*>(t->mem + o_rep);
     t->rep = reinterpret_cast<int32_t*>(t->mem + o_flags);
@@ -818,8 +984,8 @@ int cnmf_adj_forward(cnmf_ctx* c, int64_t n, int64_t m, const float* X, int64_t 
     t->Gb = F(i++); t->Fb = F(i++); t->Gb2 = F(i++); t->Fb2 = F(i++);
     t->XRb = F(i++); t->XLb = F(i++); t->QLb = F(i++); t->QRb = F(i++);
     t->GL = F(i++); t->FR = F(i++);
-    t->Bsub = F(i++); t->Bb = F(i++); t->Wb = F(i++);
-    t->GLb = F(i++); t->FRb = F(i++); t->v = F(i++);
+    t->Bsub = F(i++); t->Bsub2 = F(i++); t->Bb = F(i++);
+    t->Wb = F(i++); t->GLb = F(i++); t->FRb = F(i++);
     t->Zs = F(i++);
     t->Wpart = reinterpret_cast<double*>(t->mem + o_wp);
     t->Lpart = reinterpret_cast<double*>(t->mem + o_lp);
@@ -888,6 +1054,12 @@ int cnmf_adj_backward(cnmf_tape* t, const float* dG, const float* dF, float* dX,
         CK(hipMemcpyAsync(t->Tm, t->Fc[s], (size_t)p * m * 4, hipMemcpyDeviceToDevice, d.stream));
         int rc = solve_span(t, t->Tn, t->Tm, t0, cnt, true);
         if (rc) return rc;
+        // top eigenvectors of every W of the segment
+        if (t->p <= 16)
+            hipLaunchKernelGGL(k_eigvec<16>, dim3(2 * cnt), dim3(64), 0, d.stream, t->p, t->Wh, t->Lh, t->Vh);
+        else
+            hipLaunchKernelGGL(k_eigvec<32>, dim3(2 * cnt), dim3(64), 0, d.stream, t->p, t->Wh, t->Lh, t->Vh);
+        CK(hipGetLastError());
         for (int j = cnt - 1; j >= 0; --j) {
             const float* Gcur = t->Gh + (size_t)j * n * p;
             const float* Gprev = j > 0 ? t->Gh + (size_t)(j - 1) * n * p : t->Gc[s];

@@ -44,8 +44,13 @@ def _gpu_loss_grad(inst, Gt, Ft, q, T, K, ckpt):
 
 @pytest.mark.parametrize("n,m,p,nu,q,T,K,ckpt", [(60, 45, 3, 5, 2, 3, 5, 2),
                                                  (200, 150, 5, 10, 2, 6, 5, 4),
-                                                 (300, 260, 10, 10, 2, 10, 5, 10)])
+                                                 (300, 260, 10, 10, 2, 10, 5, 10),
+                                                 (130, 110, 16, 4, 1, 3, 8, 2),
+                                                 (170, 140, 21, 5, 1, 4, 6, 3)])
 def test_adjoint_matches_fp64_reference(n, m, p, nu, q, T, K, ckpt):
+    """Ranks up to 16 keep the reverse's iterates in LDS, wider ranks in an
+    HBM tape; K = 8 is the longest inner loop the reverse supports; 130 and
+    170 rows leave ragged last workgroups."""
     say("adjoint_ref", n, m, p, nu, q, T, K, ckpt)
     inst, Gt, Ft = _case(n, m, p, nu, seed=n)
     Lg, gX, gG, gF, G, F = _gpu_loss_grad(inst, Gt, Ft, q, T, K, ckpt)
