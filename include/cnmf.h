@@ -273,6 +273,17 @@ int cnmf_sweep_left(cnmf_ctx* ctx, int64_t R, int64_t C, const float* X,
                     int64_t ldx, int32_t k, const float* B, int64_t ldb,
                     float* Z, int64_t ldz, int32_t z_trans);
 
+/* Both sweeps from one read of X, as every half-step of Algorithm 2 needs
+ * them (one product per chain): Y (R x k, ldy) = X * A with A given as its
+ * transpose AT (k x C, row pitch ldat), and Z = X^T * B (B R x k, ldb)
+ * written C x k (z_trans = 0) or k x C (z_trans = 1), row pitch ldz.
+ * FP32 MFMA, FP32 accumulation, results bitwise reproducible.  R, C >= 1,
+ * 1 <= k <= 32; Y and Z must not overlap the inputs. */
+int cnmf_sweep_dual(cnmf_ctx* ctx, int64_t R, int64_t C, const float* X,
+                    int64_t ldx, int32_t k, const float* AT, int64_t ldat,
+                    const float* B, int64_t ldb, float* Y, int64_t ldy,
+                    float* Z, int64_t ldz, int32_t z_trans);
+
 /* BF16 form of the two sweeps (the precision form of the X-sized products
  * of Algorithm 2): Xb holds X as bfloat16 bit patterns (R x C, row pitch
  * ldxb >= C, any alignment); the skinny operand is rounded to bfloat16

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcnmf.so")
-SOURCES = ["api.hip", "batch.hip", "adjoint.hip", "sweep.hip", "sweep_bf16.hip", "orth.hip", "small.hip", "solver.hip"]
+SOURCES = ["api.hip", "batch.hip", "adjoint.hip", "sweep.hip", "sweep_dual.hip", "sweep_bf16.hip", "orth.hip", "small.hip", "solver.hip"]
 ARCH = os.environ.get("CNMF_ARCH", "gfx950")
 
 FLAGS = [

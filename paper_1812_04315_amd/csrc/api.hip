@@ -193,6 +193,22 @@ int cnmf_sweep_right(cnmf_ctx* c, int64_t R, int64_t C, const float* X, int64_t 
                                 at<float>(c, off)));
 }
 
+int cnmf_sweep_dual(cnmf_ctx* c, int64_t R, int64_t C, const float* X, int64_t ldx, int32_t k,
+                    const float* AT, int64_t ldat, const float* B, int64_t ldb, float* Y,
+                    int64_t ldy, float* Z, int64_t ldz, int32_t z_trans) {
+    if (!c || R < 1 || C < 1 || k < 1 || k > 32) return CNMF_EINVAL;
+    if (bad_ptr(X) || bad_ptr(AT) || bad_ptr(B) || bad_ptr(Y) || bad_ptr(Z)) return CNMF_EINVAL;
+    if (ldx < C || ldat < C || ldb < k || ldy < k || (z_trans ? ldz < C : ldz < k))
+        return CNMF_EINVAL;
+    Arena a;
+    size_t off = a.take<float>(sweep_dual_partial_floats(c->dev, R, C));
+    int rc = ensure_ws(c, a.off);
+    if (rc) return rc;
+    if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
+    return from_hip(sweep_dual(c->dev, R, C, X, ldx, k, AT, ldat, B, ldb, Y, ldy, Z, ldz,
+                               z_trans != 0, at<float>(c, off)));
+}
+
 int cnmf_sweep_left(cnmf_ctx* c, int64_t R, int64_t C, const float* X, int64_t ldx, int32_t k,
                     const float* B, int64_t ldb, float* Z, int64_t ldz, int32_t z_trans) {
     if (!c || R < 0 || C < 0 || k < 1 || k > 32) return CNMF_EINVAL;
@@ -320,8 +336,9 @@ int rsi_run(cnmf_ctx* c, int64_t n, int64_t m, const float* X, const uint16_t* X
     const size_t o_oLT = a.take<float>((size_t)l * ldt);
     const size_t o_QRtT = a.take<float>((size_t)l * ldt);
     const size_t o_QLtT = a.take<float>((size_t)l * ldt);
-    size_t part = std::max(sweep_right_partial_floats(c->dev, n, m),
-                           sweep_left_partial_floats(c->dev, n, m));
+    size_t part = bf ? std::max(sweep_right_partial_floats(c->dev, n, m),
+                                sweep_left_partial_floats(c->dev, n, m))
+                     : sweep_dual_partial_floats(c->dev, n, m);
     if (bf)
         part = std::max(part, std::max(sweep_right_bf16_partial_floats(c->dev, n, m),
                                        sweep_left_bf16_partial_floats(c->dev, n, m)));
@@ -350,8 +367,15 @@ int rsi_run(cnmf_ctx* c, int64_t n, int64_t m, const float* X, const uint16_t* X
     };
     auto left = [&](const float* B, float* Z, bool trans) -> hipError_t {  // Z = X^T B
         const int64_t ldz = trans ? m : l;
-        if (bf) return sweep_left_bf16(d, n, m, Xb, ldx, l, B, l, Z, ldz, trans, pt);
-        return sweep_left(d, n, m, X, ldx, l, B, l, Z, ldz, trans, pt);
+        return sweep_left_bf16(d, n, m, Xb, ldx, l, B, l, Z, ldz, trans, pt);
+    };
+    // Y = X A and Z = X^T B, one product for each chain: FP32 in one read of X
+    auto both = [&](const float* AT, float* Y, const float* B, float* Z, bool trans) -> hipError_t {
+        if (bf) {
+            const hipError_t e = right(AT, Y);
+            return e != hipSuccess ? e : left(B, Z, trans);
+        }
+        return sweep_dual(d, n, m, X, ldx, l, AT, ldt, B, l, Y, l, Z, trans ? m : l, trans, pt);
     };
     // orthonormal bases of an n-space panel Yn_ (n x l, pool Omega_R^T) and an
     // m-space panel Ym_ (m x l, pool Omega_L) at once (independent panels);
@@ -376,22 +400,19 @@ int rsi_run(cnmf_ctx* c, int64_t n, int64_t m, const float* X, const uint16_t* X
     // The two chains (left and right bases) are independent: each pair of
     // bases that both chains need at the same point is found in one launch.
     // Step 0: sketches X Omega_L and (Omega_R X)^T and their bases.
-    CK(right(oLT, Yn));
-    CK(left(oRt, Ym, false));
+    CK(both(oLT, Yn, oRt, Ym, false));
     CK(orth_nm(Yn, QL, Ym, QRt, QRtT));
     for (int k = 1; k <= prm->q; ++k) {
         // Q~_L^(k) = orth(X^T Q_L^(k-1)), kept in the Q_R output (m x l), and
         // Q~_R^(k)^T = orth(X Q_R^(k-1)^T), kept in the Q_L output (n x l).
-        CK(left(QL, Ym, false));
-        CK(right(QRtT, Yn));
+        CK(both(QRtT, Yn, QL, Ym, false));
         CK(orth_nm(Yn, QL_out, Ym, QR_out, QLtT));
         // X Q~_L^(k) (n x l) and (Q~_R^(k) X)^T (m x l).
-        CK(right(QLtT, XR_out));
         if (k < prm->q) {
-            CK(left(QL_out, Ym, false));
+            CK(both(QLtT, XR_out, QL_out, Ym, false));
             CK(orth_nm(XR_out, QL, Ym, QRt, QRtT));
         } else {
-            CK(left(QL_out, XL_out, true));   // X_L = Q_L^T X, l x m
+            CK(both(QLtT, XR_out, QL_out, XL_out, true));   // X_L = Q_L^T X, l x m
         }
     }
     return CNMF_OK;

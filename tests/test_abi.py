@@ -40,6 +40,8 @@ def test_null_context_and_bad_arguments(lib):
     import paper_1812_04315_amd as cnmf
     assert lib.cnmf_sweep_right(None, 1, 1, None, 1, 1, None, 1, 0, None, 1) == cnmf.EINVAL
     assert lib.cnmf_sweep_left(None, 1, 1, None, 1, 1, None, 1, None, 1, 0) == cnmf.EINVAL
+    assert lib.cnmf_sweep_dual(None, 1, 1, None, 1, 1, None, 1, None, 1, None, 1, None, 1,
+                               0) == cnmf.EINVAL
     assert lib.cnmf_orth(None, 4, 2, None, None, 0, 1e-9, None, None) == cnmf.EINVAL
     assert lib.cnmf_lipschitz(None, 3, None, None) == cnmf.EINVAL
     prm = cnmf.params(5)

@@ -48,6 +48,41 @@ def test_sweep_left(R, C, k, ld, z_trans):
     assert np.all(np.abs(Z - ref) <= 1e-5 * _bound(X.T, B) + 1e-30)
 
 
+@pytest.mark.parametrize("R,C,k,ld,ldat", [
+    (1, 1, 1, None, None), (31, 33, 5, None, None), (200, 150, 15, None, 151),
+    (257, 1000, 25, 1003, None), (1000, 97, 32, 100, 100), (64, 4096, 16, 4096, None),
+    (3, 2000, 7, None, 2001), (513, 777, 30, 780, 777), (2000, 3, 17, None, None),
+    (4100, 2304, 25, None, None)])
+@pytest.mark.parametrize("z_trans", [False, True])
+def test_sweep_dual(R, C, k, ld, ldat, z_trans):
+    """Both products of one read of X (every half-step of Algorithm 2):
+    ragged rows and columns, unaligned pitches of X and of the A panel,
+    column tiles and row slices (4100 x 2304: nine full tiles, several
+    slices)."""
+    say("sweep_dual", R, C, k, ld, ldat, z_trans)
+    rng = np.random.default_rng(R * 3 + C + k)
+    X = rng.random((R, C)).astype(np.float32)
+    A = rng.standard_normal((C, k)).astype(np.float32)
+    B = rng.standard_normal((R, k)).astype(np.float32)
+    Y, Z = cnmf.sweep_dual(dev(X, ld), dev(A.T.copy(), ldat), dev(B), z_trans=z_trans)
+    Y, Z = host(Y), host(Z)
+    if z_trans:
+        Z = Z.T
+    X64 = X.astype(np.float64)
+    assert np.all(np.abs(Y - X64 @ A.astype(np.float64)) <= 1e-5 * _bound(X, A) + 1e-30)
+    assert np.all(np.abs(Z - X64.T @ B.astype(np.float64)) <= 1e-5 * _bound(X.T, B) + 1e-30)
+
+
+def test_sweep_dual_bitwise_repeatable():
+    rng = np.random.default_rng(1)
+    X = dev(rng.random((3000, 2000)))
+    AT = dev(rng.standard_normal((25, 2000)))
+    B = dev(rng.standard_normal((3000, 25)))
+    a = [host(t) for t in cnmf.sweep_dual(X, AT, B)]
+    b = [host(t) for t in cnmf.sweep_dual(X, AT, B)]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 def test_sweep_bitwise_repeatable():
     rng = np.random.default_rng(0)
     X = dev(rng.random((3000, 2000)))
