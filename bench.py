@@ -448,7 +448,8 @@ def bench_bf16(args, torch, cnmf, synth):
     for nm_, f in (("right_bf16", lambda: cnmf.sweep_right_bf16(X16, AT, a_trans=True, out=Y)),
                    ("left_bf16", lambda: cnmf.sweep_left_bf16(X16, Bp)),
                    ("right_fp32", lambda: cnmf.sweep_right(X, AT, a_trans=True, out=Y)),
-                   ("left_fp32", lambda: cnmf.sweep_left(X, Bp))):
+                   ("left_fp32", lambda: cnmf.sweep_left(X, Bp)),
+                   ("dual_fp32", lambda: cnmf.sweep_dual(X, AT, Bp))):
         for _ in range(3):
             f()
         e = _events(torch, 2)
