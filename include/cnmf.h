@@ -155,7 +155,11 @@ const char* cnmf_strerror(int code);
  *   X_L      out, l x m = Q_L^T X   (Algorithm 1's L X).
  *   X_R      out, n x l = X Q_R     (Algorithm 1's X R).
  * Two independent chains, re-orthonormalised at every half-step by
- * CholeskyQR2 with FP64 Gram and Cholesky.  A column whose Cholesky pivot
+ * CholeskyQR with FP64 Gram and Cholesky (a second pass, CholeskyQR2, when
+ * some pivot falls below 1e-7 of its diagonal entry, where one FP64 pass
+ * could leave an orthogonality loss above FP32 rounding, and after column
+ * replacements).  Both products of a half-step come from one read of X
+ * (cnmf_sweep_dual).  A column whose Cholesky pivot
  * is <= tau2 * max_j ||y_j||^2 is replaced by the same column of the other
  * Gaussian draw (Omega_R^T for n-space panels, Omega_L for m-space panels).
  * Sweeps run in FP32 (sweep_prec must be CNMF_PREC_FP32 here). */
@@ -189,7 +193,7 @@ int cnmf_rsi_bf16(cnmf_ctx* ctx, int64_t n, int64_t m, const uint16_t* Xb,
  *                           projection Sec. 3 cites): Q_R = orth((X^T X)^q
  *                           Omega_L), Q_L = orth((X X^T)^q Omega_R^T), each
  *                           intermediate product scaled to unit Frobenius norm
- *                           (ranges unchanged), one CholeskyQR2 with the rank
+ *                           (ranges unchanged), one CholeskyQR(2) with the rank
  *                           rule of cnmf_rsi at the end; the same 2q + 1
  *                           passes over X per chain as Algorithm 2, in exact
  *                           arithmetic the same subspaces, but the weak
@@ -297,7 +301,7 @@ int cnmf_sweep_left_bf16(cnmf_ctx* ctx, int64_t R, int64_t C, const uint16_t* Xb
                          int64_t ldxb, int32_t k, const float* B, int64_t ldb,
                          float* Z, int64_t ldz, int32_t z_trans);
 
-/* Orthonormal basis of Y (N x l, ld = l) by CholeskyQR2 with the rank rule
+/* Orthonormal basis of Y (N x l, ld = l) by CholeskyQR(2) with the rank rule
  * of cnmf_rsi; pool is N x l (pool_trans = 0, ld = l) or l x N
  * (pool_trans = 1, ld = N).  Q out N x l.  replaced out: l int32 flags. */
 int cnmf_orth(cnmf_ctx* ctx, int64_t N, int32_t l, const float* Y,

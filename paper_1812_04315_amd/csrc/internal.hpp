@@ -281,7 +281,8 @@ hipError_t transpose(const Dev& d, int64_t R, int64_t C, const float* A, int64_t
 hipError_t check_input(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx,
                        Control* ctl);
 
-// orth.hip: CholeskyQR2 with the rank rule in one launch.  xch: exchange
+// orth.hip: CholeskyQR (second pass when ill-conditioned) with the rank rule
+// in one launch.  xch: exchange
 // words (orth_exchange_words(), room for two panels at once; a single panel
 // uses the first half); seq: launch tag (< 2^22), fresh per call.
 // QT (optional): transposed copy of Q with row pitch ldqt.

@@ -1,16 +1,21 @@
 // Orthonormal bases for randomized subspace iteration (Sec. 3, Algorithm 2:
 // "QR decomposition", "orthonormal bases" of each sketch and half-step).
 //
-// CholeskyQR2 on an N x l FP32 panel (l <= 32), one persistent launch:
+// CholeskyQR on an N x l FP32 panel (l <= 32), one persistent launch:
 //   pass 1: W = Y^T Y in FP64, right-looking Cholesky with the numerical-
 //           rank rule; if a column is deficient, the same on the augmented
 //           W = [Y P]^T [Y P] (P = replacement pool) with the swaps;
-//           Q1 = Y^ R^-1 where Y^ is Y with deficient columns swapped for
-//           pool columns;
-//   pass 2: W = Q1^T Q1, Cholesky, Q = Q1 R2^-1.
-// The FP64 Gram of FP32 data has exact products, so pass 1 already gives
-// orthogonality near FP32 rounding for condition numbers far beyond what the
-// rank rule admits; pass 2 removes what is left.
+//           Q1 = Y^ R^-1 (FP64 arithmetic) where Y^ is Y with deficient
+//           columns swapped for pool columns;
+//   pass 2 (only for an ill-conditioned panel, see below): W = Q1^T Q1,
+//           Cholesky, Q = Q1 R2^-1 (CholeskyQR2).
+// The FP64 Gram of FP32 data has exact products, and CholeskyQR loses
+// orthogonality in proportion to eps cond^2 in the precision of its Gram and
+// factorisation, here FP64, where cond is that of Y with unit columns, about
+// 1 / sqrt(min_j pivot_j / W_jj).  While min_j pivot_j / W_jj >= 1e-7 that
+// loss is below 1e-9, under the FP32 rounding of Q itself, and a second
+// pass would only repeat that rounding: Q = Q1.  Otherwise (and after
+// column replacements) pass 2 follows.
 //
 // Rank rule: at Cholesky step j the Schur-complement pivot d_j is the squared
 // residual of column j after projection onto columns < j.  d_j <=
@@ -38,6 +43,7 @@ constexpr int kMaxW = 64;        // augmented width 2 l
 constexpr int kMaxPairs = kOrthMaxPairs;   // pairs of a 64-column Gram
 constexpr int kPairsPerThread = (kMaxPairs + kThreads - 1) / kThreads;   // 9
 constexpr int kTile = 32;
+constexpr double kPolish = 1e-7;   // min pivot ratio below which pass 2 runs
 
 __device__ __forceinline__ void xstore(uint64_t* p, unsigned tag, double v) {
     const uint64_t bits = (uint64_t)__double_as_longlong(v);
@@ -72,6 +78,7 @@ struct Shared {
     double rvec[kMaxW];
     double dinv[32];
     double ref[kMaxW];
+    double minrat;   // min_j pivot_j / W_jj of the last factorisation
     int sel[32];
     int flag;
     int timeout;
@@ -244,10 +251,13 @@ __device__ void cholesky_regs(const OrthArgs& g, Shared& sh, bool detect) {
     const double thr = g.tau2 * wave_max(myref);
     __builtin_amdgcn_wave_barrier();
     bool stop = false;
+    double minrat = 1.0;
 #pragma unroll
     for (int j = 0; j < 32; ++j) {
         if (j < l && !stop) {
             double d = lane_d(Mr[j], j);                     // M[j][j]
+            const double wjj = sh.ref[j];
+            minrat = fmin(minrat, wjj > 0.0 ? d / wjj : 0.0);
             if (detect) {
                 if (!(d > thr)) stop = true;                 // uniform
             } else if (!(d > g.tau2 * sh.ref[j])) {
@@ -269,6 +279,7 @@ __device__ void cholesky_regs(const OrthArgs& g, Shared& sh, bool detect) {
             }
         }
     }
+    if (lane == 0) sh.minrat = minrat;
     if (stop) {
         if (lane == 0) sh.flag = 1;
         __builtin_amdgcn_wave_barrier();
@@ -407,7 +418,8 @@ __device__ __forceinline__ void orth_body(const OrthArgs& g, const unsigned blk,
     // Stage 1 (only if a column of Y is deficient; every workgroup factors
     //   the same sums, so the decision is uniform): the same on the Gram of
     //   [Y P], with the swaps.  Stage 0 or 1 ends with Q1 = Y^ R^-1 in Q.
-    // Stage 2: Gram of Q1, Cholesky, Q = Q1 R2^-1 in place (pass 2).
+    // Stage 2 (after stage 1, or when stage 0 found the panel ill-conditioned;
+    //   again uniform): Gram of Q1, Cholesky, Q = Q1 R2^-1 in place (pass 2).
     // One loop body keeps a single copy of each step's code.
     if (threadIdx.x == 0) sh.flag = 0;
     int stage = 0;
@@ -429,9 +441,10 @@ __device__ __forceinline__ void orth_body(const OrthArgs& g, const unsigned blk,
         }
         if (stage < 2 && blk == 0 && g.replaced && threadIdx.x < l)
             g.replaced[threadIdx.x] = sh.sel[threadIdx.x];
-        apply_rows(g, sh, A, stage < 2, r0, r1, g.Q, stage == 2 ? g.QT : nullptr);
+        const bool last = stage == 2 || (stage == 0 && sh.minrat >= kPolish);
+        apply_rows(g, sh, A, stage < 2, r0, r1, g.Q, last ? g.QT : nullptr);
         __syncthreads();
-        stage = stage < 2 ? 2 : 3;
+        stage = last ? 3 : 2;
     }
 }
 
