@@ -498,7 +498,8 @@ def sweep_left_bf16(Xb, B, z_trans: bool = False, out=None):
 
 
 def orth(Y, pool, pool_trans: bool = False, tau2: float = 1e-9):
-    """CholeskyQR2 basis of Y (N x l) with the rank rule; returns (Q, replaced)."""
+    """CholeskyQR basis of Y (N x l) with the rank rule (second pass for an
+    ill-conditioned panel); returns (Q, replaced)."""
     torch = _torch()
     N, ell = Y.shape
     _need(Y, torch.float32, "Y", (N, ell))

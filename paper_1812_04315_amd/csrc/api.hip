@@ -599,6 +599,16 @@ int scratch_address(int device, char** out) {
 
 // The outer loop of cnmf_solve.  ws: workspace base of at least `cap`
 // bytes, or null for the context's (growing) workspace.
+// CNMF_FUSED_LOOP=0 runs the compressed outer loop as one launch per phase
+// (the form every other configuration uses), for comparison.
+bool fused_loop_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("CNMF_FUSED_LOOP");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
 int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t m,
               const float* X, int64_t ldx, const float* Q_L, const float* Q_R,
               const float* X_L, const float* X_R, const cnmf_params* prm, float* G, float* F,
@@ -633,6 +643,14 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
     const size_t o_sw = ar.take<float>(comp ? 1 : std::max(sweep_right_partial_floats(c->dev, n, m),
                                                             sweep_left_partial_floats(c->dev, n, m)));
     const size_t o_eig = ar.take<double>(4 * kEigWords);   // {L, v} per side and parity
+    // the whole outer loop in one launch: compressed Nesterov, no time budget,
+    // the default stop-test lag, row tiles the fused kernel covers
+    const bool budget = prm->time_budget > 0.0;
+    const bool fused = comp && T > 0 && prm->solver == CNMF_SOLVER_NESTEROV &&
+                       prm->restart == CNMF_RESTART_NONE && !budget && c->dlag < 0 &&
+                       fused_loop_enabled() && phase_loop_supported(p, tilesG, tilesF);
+    const size_t o_pG64 = ar.take<uint64_t>(fused ? (size_t)nbG * 1024 : 1);
+    const size_t o_pF64 = ar.take<uint64_t>(fused ? (size_t)nbF * 1024 : 1);
     if (ws) {
         if (ar.off > cap) return CNMF_ETOOBIG;
     } else {
@@ -648,6 +666,8 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
     float* BF = reinterpret_cast<float*>(ws + o_BF);
     float* sw = reinterpret_cast<float*>(ws + o_sw);
     double* eig = reinterpret_cast<double*>(ws + o_eig);
+    uint64_t* pG64 = reinterpret_cast<uint64_t*>(ws + o_pG64);
+    uint64_t* pF64 = reinterpret_cast<uint64_t*>(ws + o_pF64);
     auto eig_at = [&](int side, int par) { return eig + (size_t)(2 * side + par) * kEigWords; };
     Control* ctl = c->ctl;
     const bool global = prm->stop_rule == CNMF_STOP_GLOBAL;
@@ -699,9 +719,11 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
     fa.nin = (int)nbG;
     fa.part_out = pF;
 
+    unsigned last_seq = 0;
     auto run = [&](PhaseArgs a, bool is_g) -> hipError_t {
         hipError_t e = next_seq(c, &a.seq);
         if (e != hipSuccess) return e;
+        last_seq = a.seq;
         return phase(d, a, is_g ? nbG : nbF, is_g ? tilesG : tilesF);
     };
     auto bg = [&]() -> hipError_t {   // plain: B_G = X F^T
@@ -712,7 +734,19 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
     };
 
     if (tr.ticks) CK(write_tick(d, (unsigned long long*)tr.ticks));
-    const bool budget = prm->time_budget > 0.0;
+    if (fused) {
+        // tagged partials: tag 0 is never issued, so cleared words read as absent
+        CK(fill_u64(d, pG64, (int64_t)nbG * 1024, 0));
+        CK(fill_u64(d, pF64, (int64_t)nbF * 1024, 0));
+        ga.part_in = nullptr;
+        ga.part_out = nullptr;
+        ga.part_in64 = pF64;
+        ga.part_out64 = pG64;
+        fa.part_in = nullptr;
+        fa.part_out = nullptr;
+        fa.part_in64 = pG64;
+        fa.part_out64 = pF64;
+    }
     if (budget) {
         const double ticks = prm->time_budget * c->clock_hz;
         CK(arm_deadline(d, ctl, ticks < 1.8e19 ? (unsigned long long)ticks : ~0ull >> 1));
@@ -723,13 +757,16 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
         a.kind = 2;
         CK(run(a, false));
     }
+    unsigned seq_pF = last_seq;   // tag of the partials now in pF64 (fused)
     if (T > 0 && global) {
         // gradient bound: ratio * ||(P grad_G, P grad_F)|| at (G0, F0)
         CK(bg());
         PhaseArgs a = ga;
         a.kind = 1;
         a.pg2_out = &ctl->pg2[0];
+        a.seq_in = seq_pF;
         CK(run(a, true));
+        const unsigned seq_pG = last_seq;
         CK(bf());
         a = fa;
         a.kind = 1;
@@ -737,7 +774,44 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
         a.tol_init_from = &ctl->pg2[0];
         a.tol_init_out = &ctl->tol[0];
         a.ratio = prm->inner_ratio;
+        a.seq_in = seq_pG;
         CK(run(a, false));
+        seq_pF = last_seq;
+    }
+    if (fused) {
+        if (tr.ticks) CK(fill_u64(d, tr.ticks + 1, T, 0));
+        LoopArgs L{};
+        L.g = ga;
+        L.f = fa;
+        if (global) {
+            L.g.tol_state = &ctl->tol[0];   // marks the global rule; the loop keeps the bounds itself
+            L.f.tol_state = &ctl->tol[1];
+        } else {
+            L.g.ratio = prm->inner_ratio;
+            L.f.ratio = prm->inner_ratio;
+        }
+        if (replay) {
+            L.g.forced_ptr = replay;
+            L.f.forced_ptr = replay + 1;
+        }
+        if (tr.steps) { L.g.steps_out = tr.steps; L.f.steps_out = tr.steps + 1; }
+        if (tr.lips) { L.g.L_out = tr.lips; L.f.L_out = tr.lips + 1; }
+        if (tr.tols) { L.g.tol_out = tr.tols; L.f.tol_out = tr.tols + 1; }
+        L.g.hist = tr.G_hist;
+        L.f.hist = tr.F_hist;
+        if (tr.W_hist) { L.g.w_out = tr.W_hist; L.f.w_out = tr.W_hist + (size_t)p * p; }
+        if (tr.ticks) L.f.tick_out = (unsigned long long*)(tr.ticks + 1);
+        L.f.done_out = tr.outer_done;
+        L.T = T;
+        L.nbG = nbG;
+        L.nbF = nbF;
+        L.seq_pre = seq_pF;
+        CK(reserve_seq(c, 2u * (unsigned)T, &L.seq0));
+        L.g_hist_stride = (int64_t)n * p;
+        L.f_hist_stride = (int64_t)p * m;
+        L.global_rule = global ? 1 : 0;
+        CK(phase_loop(d, L, tilesG, tilesF));
+        return CNMF_OK;
     }
     if (tr.ticks && T > 0) CK(fill_u64(d, tr.ticks + 1, T, 0));
     // no warm start for the first subproblem of either side

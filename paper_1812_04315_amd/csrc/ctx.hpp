@@ -42,6 +42,21 @@ inline hipError_t next_seq(cnmf_ctx* c, unsigned* seq) {
     return hipSuccess;
 }
 
+// count consecutive sequence numbers for the phases of one launch; base
+// receives the first
+inline hipError_t reserve_seq(cnmf_ctx* c, unsigned count, unsigned* base) {
+    if (c->seq + count + 1 >= (1u << 22)) {
+        hipError_t e = fill_u64(c->dev, c->slots, (int64_t)kSlotWords, 0);
+        if (e != hipSuccess) return e;
+        e = fill_u64(c->dev, c->oxch, (int64_t)orth_exchange_words(), 0);
+        if (e != hipSuccess) return e;
+        c->seq = 0;
+    }
+    *base = c->seq + 1;
+    c->seq += count;
+    return hipSuccess;
+}
+
 #define CK(x)                                   \
     do {                                        \
         hipError_t e_ = (x);                    \

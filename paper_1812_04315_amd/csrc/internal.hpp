@@ -384,7 +384,35 @@ struct PhaseArgs {
     int done_value;
     const unsigned long long* deadline;
     int solver;              // kSolver*: update rule of the subproblem
+    // partial products as tagged words {seq : 32 | FP32 bits : 32} instead of
+    // part_in / part_out, for phases that follow each other inside one launch
+    // (the fused outer loop): a reader polls each word until it carries the
+    // writer's tag, so no kernel boundary is needed between the phases
+    const uint64_t* part_in64;   // [nin][32][32], written with tag seq_in
+    unsigned seq_in;
+    uint64_t* part_out64;        // [nblk][32][32], written with tag seq
 };
+
+// Whole compressed outer loop in one launch (Algorithm 1 with the Nesterov
+// inner loop of Sec. 2): for t < T, the G phase on workgroups < nbG, then the
+// F phase on workgroups < nbF.  g and f are the phases' arguments at t = 0;
+// the per-iteration outputs advance by their strides, the replayed step
+// counts by 2 per iteration, and the tags are seq0 + 2 t (G) and
+// seq0 + 2 t + 1 (F); the first G phase reads F's partials written with tag
+// seq_pre.  Every workgroup keeps the warm start of lambda_max and the
+// running bound of the global rule itself (every workgroup computes the
+// same values), so the partial products are the only data that cross
+// workgroups between phases.
+struct LoopArgs {
+    PhaseArgs g, f;
+    int T;
+    unsigned nbG, nbF;
+    unsigned seq0, seq_pre;
+    int64_t g_hist_stride, f_hist_stride;   // floats per outer iteration
+    int global_rule;                        // running bounds start from ctl->tol
+};
+hipError_t phase_loop(const Dev& d, const LoopArgs& a, int tilesG, int tilesF);
+bool phase_loop_supported(int p, int tilesG, int tilesF);
 
 // Batched launch of many subproblems (see k_phase_batched): args[count] on
 // the device, sched[rounds][slots] entries (instance << 12 | block) or

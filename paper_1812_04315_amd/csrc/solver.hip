@@ -409,15 +409,25 @@ __device__ __forceinline__ double lambda_max_warm(const double (*W)[34], double 
 
 namespace {
 
+// What a workgroup carries from one phase of a side to the next inside the
+// fused outer loop: the warm start of lambda_max (wave 0: L, and component
+// `lane` of the eigenvector) and the running bound of the global rule.
+struct PhaseState {
+    double eig_L, eig_v, tol;
+};
+
 // One subproblem (G rows or F columns) on workgroup blk of nblk; seq tags
-// the exchange words of this launch.
+// the exchange words of this launch.  st (fused outer loop only) replaces the
+// warm start read from eig_in / written to eig_out and the running bound
+// read from tol_ptr / written to tol_state.
 // SOLVER: kSolverNesterov (Sec. 2), kSolverRestart (the same loop with the
 // momentum of every row restarted adaptively; non-grouped exchange only),
 // kSolverHals or kSolverMu (fixed counts of HALS sweeps or multiplicative
 // updates; no Lipschitz constant, no stopping test).
 template <int PT, int TILES, int DLAG, int SOLVER = kSolverNesterov>
 __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned blk,
-                                           const unsigned nblk, const unsigned seq) {
+                                           const unsigned nblk, const unsigned seq,
+                                           PhaseState* st = nullptr) {
     constexpr bool ALT = SOLVER == kSolverHals || SOLVER == kSolverMu;
     constexpr bool RESTART = SOLVER == kSolverRestart;
     static_assert(!RESTART || DLAG != kGrouped, "restart runs the per-step exchange");
@@ -464,7 +474,12 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     // warm start of lambda_max (wave 0), fetched now so the load is in
     // flight during the exchange of S
     double eig_L = 0.0, eig_v = 0.0;
-    if (a.kind == 0 && a.eig_in && wave == 0) {
+    if (st) {
+        if (a.kind == 0 && wave == 0) {
+            eig_L = st->eig_L;
+            eig_v = lane < p ? st->eig_v : 0.0;
+        }
+    } else if (a.kind == 0 && a.eig_in && wave == 0) {
         eig_L = a.eig_in[0];
         const double e = a.eig_in[1 + (lane < p ? lane : p - 1)];
         eig_v = lane < p ? e : 0.0;
@@ -524,7 +539,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                     const int k = 16 * hm + q16;
                     const int64_t rc = r < a.rows ? r : rlast;
                     const int kc = k < a.ell ? k : a.ell - 1;
-                    const float qv = (has_rows && a.mode == 2 && a.part_out) ? a.Q[rc * a.ell + kc] : 0.f;
+                    const float qv = (has_rows && a.mode == 2 && (a.part_out || a.part_out64)) ? a.Q[rc * a.ell + kc] : 0.f;
                     qpre[t][s][hm] = (r < a.rows && k < a.ell) ? qv : 0.f;
                 }
     }
@@ -548,7 +563,26 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         for (int e = (int)blk + (int)nblk * wave; e < nS; e += (int)nblk * 4) {
             const int mr = e / p, nc = e % p;
             double t = 0.0;
-            for (int j = lane; j < a.nin; j += 64) t += (double)a.part_in[(size_t)j * 1024 + mr * 32 + nc];
+            if (a.part_in64) {
+                // tagged partials of the phase before, written in this launch
+                for (int j = lane; j < a.nin; j += 64) {
+                    const uint64_t* wp = &a.part_in64[(size_t)j * 1024 + mr * 32 + nc];
+                    uint64_t w = slot_load(wp);
+                    unsigned spins = 0;
+                    while ((unsigned)(w >> 32) != a.seq_in) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if ((++spins & 255u) == 0u &&
+                            (spins >= kSpinLimit || (atomic_status_load(&ctl->status) & CNMF_ST_TIMEOUT))) {
+                            raise_status(ctl, CNMF_ST_TIMEOUT);
+                            break;
+                        }
+                        w = slot_load(wp);
+                    }
+                    t += (double)__uint_as_float((uint32_t)w);
+                }
+            } else {
+                for (int j = lane; j < a.nin; j += 64) t += (double)a.part_in[(size_t)j * 1024 + mr * 32 + nc];
+            }
             t = wave_sum(t);
             if (lane == 0) slot_store(&a.slot_s[e], seq, __float_as_uint((float)t));
         }
@@ -613,7 +647,10 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         double ev;
         const double lm = lambda_max_warm<16 * PT>(sWd, sM, p, eig_L, eig_v, ev, swv, sdg, seo, sv);
         if (lane == 0) s_L = lm;
-        if (a.eig_out && blk == 0) {
+        if (st) {
+            st->eig_L = (lm > 0.0 && lm == lm) ? lm : 0.0;
+            st->eig_v = lane < p ? ev : 0.0;
+        } else if (a.eig_out && blk == 0) {
             if (lane == 0) a.eig_out[0] = (lm > 0.0 && lm == lm) ? lm : 0.0;
             if (lane < p) a.eig_out[1 + lane] = ev;
         }
@@ -767,7 +804,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
         if (s_flag) ok = false;
     }
 
-    double tol = a.tol_ptr ? *a.tol_ptr : a.tol_value;
+    double tol = st ? st->tol : (a.tol_ptr ? *a.tol_ptr : a.tol_value);
     if (a.ratio > 0.0 && a.kind == 0) tol = a.ratio * sqrt(pg0);
     const double tol2 = tol >= 0.0 ? tol * tol : -1.0;   // the test is ||pg||^2 <= tol^2
     const int forced = a.forced_ptr ? (int)*a.forced_ptr : a.forced;
@@ -1226,7 +1263,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 }
         }
     }
-    if (a.part_out) {
+    if (a.part_out || a.part_out64) {
         // partial = sum over rows of q_r (x) z_r (mode 2, l x p) or z_r (x) z_r (p x p)
         constexpr int MT = 2;   // M tiles (l <= 32 or p <= 32)
         v4f acc[MT][PT];
@@ -1287,8 +1324,9 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             const int M = 16 * hm + 4 * (l >> 4) + i;
             const int N = 16 * hn + (l & 15);
             const float s = (sred[0][ri][l] + sred[1][ri][l]) + (sred[2][ri][l] + sred[3][ri][l]);
-            if (hn < PT) a.part_out[(size_t)blk * 1024 + M * 32 + N] = s;
-            else a.part_out[(size_t)blk * 1024 + M * 32 + N] = 0.f;
+            const float v = hn < PT ? s : 0.f;
+            if (a.part_out64) slot_store(&a.part_out64[(size_t)blk * 1024 + M * 32 + N], seq, __float_as_uint(v));
+            else a.part_out[(size_t)blk * 1024 + M * 32 + N] = v;
         }
     }
 
@@ -1304,13 +1342,17 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 a.tol_init_out[1] = tt;
                 if (!isfinite(tt)) raise_status(ctl, CNMF_ST_NONFINITE);
             }
-            if (!ALT && a.kind == 0 && a.tol_state && steps >= 1 && steps <= a.inner_min)
+            if (!st && !ALT && a.kind == 0 && a.tol_state && steps >= 1 && steps <= a.inner_min)
                 a.tol_state[0] = tol / 10.0;
             if (a.done_out) a.done_out[0] = a.done_value;
             if (a.deadline && a.stop_flag && wall_clock64() > *a.deadline) *a.stop_flag = 1;
         }
         if (a.tick_out) atomicMax(a.tick_out, (unsigned long long)wall_clock64());
     }
+    // the running bound of the global rule: every workgroup took the same
+    // decision with the same steps, so each keeps the same copy
+    if (st && !ALT && a.kind == 0 && a.tol_state && steps >= 1 && steps <= a.inner_min)
+        st->tol = tol / 10.0;
 }
 
 template <int PT, int TILES, int DLAG, int SOLVER = kSolverNesterov>
@@ -1350,6 +1392,63 @@ hipError_t launch2(const Dev& d, const PhaseArgs& a, unsigned nblk) {
         case 3: return launch3<PT, TILES, 3>(d, a, nblk);
         default: return launch3<PT, TILES, 4>(d, a, nblk);
     }
+}
+
+// The whole compressed outer loop in one launch (see LoopArgs): the G phase
+// on workgroups < nbG, then the F phase on workgroups < nbF, T times.  The
+// stop-test lag is the default one of each side's tile count.
+template <int PT, int TG, int TF>
+__global__ __launch_bounds__(kThreads) void k_phase_loop(LoopArgs L) {
+    constexpr int DG = PT * TG <= 2 ? kGrouped : 2;
+    constexpr int DF = PT * TF <= 2 ? kGrouped : 2;
+    const unsigned blk = blockIdx.x;
+    const int p = L.g.p;
+    PhaseState sg{0.0, 0.0, 0.0}, sf{0.0, 0.0, 0.0};
+    if (L.global_rule) {   // written by the launches before this one
+        sg.tol = L.g.ctl->tol[0];
+        sf.tol = L.g.ctl->tol[1];
+    }
+    for (int t = 0; t < L.T; ++t) {
+        if (blk < L.nbG) {
+            PhaseArgs a = L.g;
+            a.seq = L.seq0 + 2u * (unsigned)t;
+            a.seq_in = t == 0 ? L.seq_pre : a.seq - 1u;
+            if (a.forced_ptr) a.forced_ptr += 2 * t;
+            if (a.steps_out) a.steps_out += 2 * t;
+            if (a.L_out) a.L_out += 2 * t;
+            if (a.tol_out) a.tol_out += 2 * t;
+            if (a.hist) a.hist += (int64_t)t * L.g_hist_stride;
+            if (a.w_out) a.w_out += (int64_t)(2 * t) * p * p;
+            phase_body<PT, TG, DG>(a, blk, L.nbG, a.seq, &sg);
+        }
+        if (blk < L.nbF) {
+            PhaseArgs a = L.f;
+            a.seq = L.seq0 + 2u * (unsigned)t + 1u;
+            a.seq_in = a.seq - 1u;
+            if (a.forced_ptr) a.forced_ptr += 2 * t;
+            if (a.steps_out) a.steps_out += 2 * t;
+            if (a.L_out) a.L_out += 2 * t;
+            if (a.tol_out) a.tol_out += 2 * t;
+            if (a.hist) a.hist += (int64_t)t * L.f_hist_stride;
+            if (a.w_out) a.w_out += (int64_t)(2 * t) * p * p;
+            if (a.tick_out) a.tick_out += t;
+            a.done_value = t + 1;
+            phase_body<PT, TF, DF>(a, blk, L.nbF, a.seq, &sf);
+        }
+    }
+}
+
+template <int PT, int TG, int TF>
+hipError_t launch_loop3(const Dev& d, const LoopArgs& a) {
+    const unsigned nb = a.nbG > a.nbF ? a.nbG : a.nbF;
+    hipLaunchKernelGGL((k_phase_loop<PT, TG, TF>), dim3(nb), dim3(kThreads), 0, d.stream, a);
+    return hipGetLastError();
+}
+
+template <int PT>
+hipError_t launch_loop(const Dev& d, const LoopArgs& a, int tg, int tf) {
+    if (tg == 1) return tf == 1 ? launch_loop3<PT, 1, 1>(d, a) : launch_loop3<PT, 1, 2>(d, a);
+    return tf == 1 ? launch_loop3<PT, 2, 1>(d, a) : launch_loop3<PT, 2, 2>(d, a);
 }
 
 template <int PT>
@@ -1447,6 +1546,19 @@ hipError_t phase_batched(const Dev& d, const BatchLaunch& b, int tiles, int dlag
         case 2: return launch_batched2<2>(d, b, dlag);
         default: return launch_batched2<4>(d, b, dlag);
     }
+}
+
+bool phase_loop_supported(int p, int tilesG, int tilesF) {
+    return p >= 1 && p <= 32 && (tilesG == 1 || tilesG == 2) && (tilesF == 1 || tilesF == 2);
+}
+
+hipError_t phase_loop(const Dev& d, const LoopArgs& a, int tilesG, int tilesF) {
+    if (!phase_loop_supported(a.g.p, tilesG, tilesF) || a.T < 1 || a.g.mode != 2 || a.f.mode != 2 ||
+        a.g.solver != kSolverNesterov || a.f.solver != kSolverNesterov || !a.g.part_in64 ||
+        !a.g.part_out64 || !a.f.part_in64 || !a.f.part_out64 || a.g.stop_flag || a.f.stop_flag)
+        return hipErrorInvalidValue;
+    if (a.g.p <= 16) return launch_loop<1>(d, a, tilesG, tilesF);
+    return launch_loop<2>(d, a, tilesG, tilesF);
 }
 
 hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles) {

@@ -111,6 +111,27 @@ def test_orth_full_rank(N, ell):
     assert np.linalg.norm(Qh.T @ Qh - np.eye(ell)) <= 1e-5
 
 
+@pytest.mark.parametrize("delta,tau2", [(3e-4, 1e-9), (1e-6, 1e-14), (1e-2, 1e-9)])
+def test_orth_nearly_collinear_columns(delta, tau2):
+    """Columns y_j = y_0 + delta n_j: the pivots fall to about delta^2 of the
+    diagonal.  At delta = 1e-2 one FP64 CholeskyQR pass is kept; at 3e-4 and
+    1e-6 (with a rank threshold that keeps every column) the second pass runs,
+    and at 1e-6 it is needed: one pass would leave an orthogonality loss near
+    eps64 / delta^4 = 1e-4.  Orthonormal to FP32 rounding and spanning Y."""
+    say("orth_collinear", delta, tau2)
+    rng = np.random.default_rng(8)
+    N, ell = 3000, 10
+    y0 = rng.standard_normal((N, 1))
+    Y = (y0 + delta * rng.standard_normal((N, ell))).astype(np.float32)
+    P = rng.standard_normal((N, ell)).astype(np.float32)
+    Q, rep = cnmf.orth(dev(Y), dev(P), tau2=tau2)
+    Qh = host(Q)
+    assert not host(rep).any()
+    assert np.linalg.norm(Qh.T @ Qh - np.eye(ell)) <= 1e-5
+    Y64 = Y.astype(np.float64)
+    assert np.linalg.norm(Y64 - Qh @ (Qh.T @ Y64)) <= 1e-5 * np.linalg.norm(Y64)
+
+
 @pytest.mark.parametrize("pool_trans", [False, True])
 def test_orth_rank_deficient(pool_trans):
     say("orth_rank_deficient", pool_trans)
