@@ -651,6 +651,7 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
                        fused_loop_enabled() && phase_loop_supported(p, tilesG, tilesF);
     const size_t o_pG64 = ar.take<uint64_t>(fused ? (size_t)nbG * 1024 : 1);
     const size_t o_pF64 = ar.take<uint64_t>(fused ? (size_t)nbF * 1024 : 1);
+    const size_t o_largs = ar.take<LoopArgs>(1);
     if (ws) {
         if (ar.off > cap) return CNMF_ETOOBIG;
     } else {
@@ -810,7 +811,7 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
         L.g_hist_stride = (int64_t)n * p;
         L.f_hist_stride = (int64_t)p * m;
         L.global_rule = global ? 1 : 0;
-        CK(phase_loop(d, L, tilesG, tilesF));
+        CK(phase_loop(d, L, reinterpret_cast<LoopArgs*>(ws + o_largs), tilesG, tilesF));
         return CNMF_OK;
     }
     if (tr.ticks && T > 0) CK(fill_u64(d, tr.ticks + 1, T, 0));

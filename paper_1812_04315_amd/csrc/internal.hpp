@@ -411,7 +411,8 @@ struct LoopArgs {
     int64_t g_hist_stride, f_hist_stride;   // floats per outer iteration
     int global_rule;                        // running bounds start from ctl->tol
 };
-hipError_t phase_loop(const Dev& d, const LoopArgs& a, int tilesG, int tilesF);
+hipError_t phase_loop(const Dev& d, const LoopArgs& a, LoopArgs* dev_args, int tilesG,
+                      int tilesF);   // dev_args: device memory for one LoopArgs
 bool phase_loop_supported(int p, int tilesG, int tilesF);
 
 // Batched launch of many subproblems (see k_phase_batched): args[count] on

@@ -1397,18 +1397,24 @@ hipError_t launch2(const Dev& d, const PhaseArgs& a, unsigned nblk) {
 // The whole compressed outer loop in one launch (see LoopArgs): the G phase
 // on workgroups < nbG, then the F phase on workgroups < nbF, T times.  The
 // stop-test lag is the default one of each side's tile count.
+// The arguments live in device memory and each phase reads its own copy
+// after a compiler barrier: nothing of one phase's arguments stays live in
+// scalar registers across the other phase.
 template <int PT, int TG, int TF>
-__global__ __launch_bounds__(kThreads) void k_phase_loop(LoopArgs L) {
+__global__ __launch_bounds__(kThreads) void k_phase_loop(const LoopArgs* __restrict__ Lp) {
     constexpr int DG = PT * TG <= 2 ? kGrouped : 2;
     constexpr int DF = PT * TF <= 2 ? kGrouped : 2;
     const unsigned blk = blockIdx.x;
-    const int p = L.g.p;
+    const int T = Lp->T;
     PhaseState sg{0.0, 0.0, 0.0}, sf{0.0, 0.0, 0.0};
-    if (L.global_rule) {   // written by the launches before this one
-        sg.tol = L.g.ctl->tol[0];
-        sf.tol = L.g.ctl->tol[1];
+    if (Lp->global_rule) {   // written by the launches before this one
+        sg.tol = Lp->g.ctl->tol[0];
+        sf.tol = Lp->g.ctl->tol[1];
     }
-    for (int t = 0; t < L.T; ++t) {
+    for (int t = 0; t < T; ++t) {
+        asm volatile("" ::: "memory");
+        const LoopArgs& L = *Lp;
+        const int p = L.g.p;
         if (blk < L.nbG) {
             PhaseArgs a = L.g;
             a.seq = L.seq0 + 2u * (unsigned)t;
@@ -1433,22 +1439,23 @@ __global__ __launch_bounds__(kThreads) void k_phase_loop(LoopArgs L) {
             if (a.w_out) a.w_out += (int64_t)(2 * t) * p * p;
             if (a.tick_out) a.tick_out += t;
             a.done_value = t + 1;
+            asm volatile("" ::: "memory");
             phase_body<PT, TF, DF>(a, blk, L.nbF, a.seq, &sf);
         }
     }
 }
 
 template <int PT, int TG, int TF>
-hipError_t launch_loop3(const Dev& d, const LoopArgs& a) {
+hipError_t launch_loop3(const Dev& d, const LoopArgs& a, const LoopArgs* dev_args) {
     const unsigned nb = a.nbG > a.nbF ? a.nbG : a.nbF;
-    hipLaunchKernelGGL((k_phase_loop<PT, TG, TF>), dim3(nb), dim3(kThreads), 0, d.stream, a);
+    hipLaunchKernelGGL((k_phase_loop<PT, TG, TF>), dim3(nb), dim3(kThreads), 0, d.stream, dev_args);
     return hipGetLastError();
 }
 
 template <int PT>
-hipError_t launch_loop(const Dev& d, const LoopArgs& a, int tg, int tf) {
-    if (tg == 1) return tf == 1 ? launch_loop3<PT, 1, 1>(d, a) : launch_loop3<PT, 1, 2>(d, a);
-    return tf == 1 ? launch_loop3<PT, 2, 1>(d, a) : launch_loop3<PT, 2, 2>(d, a);
+hipError_t launch_loop(const Dev& d, const LoopArgs& a, const LoopArgs* da, int tg, int tf) {
+    if (tg == 1) return tf == 1 ? launch_loop3<PT, 1, 1>(d, a, da) : launch_loop3<PT, 1, 2>(d, a, da);
+    return tf == 1 ? launch_loop3<PT, 2, 1>(d, a, da) : launch_loop3<PT, 2, 2>(d, a, da);
 }
 
 template <int PT>
@@ -1552,13 +1559,17 @@ bool phase_loop_supported(int p, int tilesG, int tilesF) {
     return p >= 1 && p <= 32 && (tilesG == 1 || tilesG == 2) && (tilesF == 1 || tilesF == 2);
 }
 
-hipError_t phase_loop(const Dev& d, const LoopArgs& a, int tilesG, int tilesF) {
+hipError_t phase_loop(const Dev& d, const LoopArgs& a, LoopArgs* dev_args, int tilesG, int tilesF) {
     if (!phase_loop_supported(a.g.p, tilesG, tilesF) || a.T < 1 || a.g.mode != 2 || a.f.mode != 2 ||
         a.g.solver != kSolverNesterov || a.f.solver != kSolverNesterov || !a.g.part_in64 ||
         !a.g.part_out64 || !a.f.part_in64 || !a.f.part_out64 || a.g.stop_flag || a.f.stop_flag)
         return hipErrorInvalidValue;
-    if (a.g.p <= 16) return launch_loop<1>(d, a, tilesG, tilesF);
-    return launch_loop<2>(d, a, tilesG, tilesF);
+    // the argument block goes to device memory ahead of the launch (a copy
+    // from pageable memory returns once the source has been read)
+    hipError_t e = hipMemcpyAsync(dev_args, &a, sizeof(LoopArgs), hipMemcpyHostToDevice, d.stream);
+    if (e != hipSuccess) return e;
+    if (a.g.p <= 16) return launch_loop<1>(d, a, dev_args, tilesG, tilesF);
+    return launch_loop<2>(d, a, dev_args, tilesG, tilesF);
 }
 
 hipError_t phase(const Dev& d, const PhaseArgs& a, unsigned nblk, int tiles) {
