@@ -643,15 +643,16 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
     const size_t o_sw = ar.take<float>(comp ? 1 : std::max(sweep_right_partial_floats(c->dev, n, m),
                                                             sweep_left_partial_floats(c->dev, n, m)));
     const size_t o_eig = ar.take<double>(4 * kEigWords);   // {L, v} per side and parity
-    // the whole outer loop in one launch: compressed Nesterov, no time budget,
-    // the default stop-test lag, row tiles the fused kernel covers
+    // the whole outer loop in one launch: compressed Nesterov, the default
+    // stop-test lag, row tiles the fused kernel covers
     const bool budget = prm->time_budget > 0.0;
     const bool fused = comp && T > 0 && prm->solver == CNMF_SOLVER_NESTEROV &&
-                       prm->restart == CNMF_RESTART_NONE && !budget && c->dlag < 0 &&
+                       prm->restart == CNMF_RESTART_NONE && c->dlag < 0 &&
                        fused_loop_enabled() && phase_loop_supported(p, tilesG, tilesF);
     const size_t o_pG64 = ar.take<uint64_t>(fused ? (size_t)nbG * 1024 : 1);
     const size_t o_pF64 = ar.take<uint64_t>(fused ? (size_t)nbF * 1024 : 1);
     const size_t o_largs = ar.take<LoopArgs>(1);
+    const size_t o_stopw = ar.take<uint64_t>(1);
     if (ws) {
         if (ar.off > cap) return CNMF_ETOOBIG;
     } else {
@@ -739,6 +740,7 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
         // tagged partials: tag 0 is never issued, so cleared words read as absent
         CK(fill_u64(d, pG64, (int64_t)nbG * 1024, 0));
         CK(fill_u64(d, pF64, (int64_t)nbF * 1024, 0));
+        CK(fill_u64(d, reinterpret_cast<uint64_t*>(ws + o_stopw), 1, 0));
         ga.part_in = nullptr;
         ga.part_out = nullptr;
         ga.part_in64 = pF64;
@@ -803,6 +805,10 @@ int solve_run(cnmf_ctx* c, char* ws, size_t cap, int method, int64_t n, int64_t 
         if (tr.W_hist) { L.g.w_out = tr.W_hist; L.f.w_out = tr.W_hist + (size_t)p * p; }
         if (tr.ticks) L.f.tick_out = (unsigned long long*)(tr.ticks + 1);
         L.f.done_out = tr.outer_done;
+        if (budget) {   // block 0 publishes its verdict after every F phase
+            L.f.deadline = &ctl->deadline;
+            L.f.stop_word = reinterpret_cast<uint64_t*>(ws + o_stopw);
+        }
         L.T = T;
         L.nbG = nbG;
         L.nbF = nbF;

@@ -391,6 +391,9 @@ struct PhaseArgs {
     const uint64_t* part_in64;   // [nin][32][32], written with tag seq_in
     unsigned seq_in;
     uint64_t* part_out64;        // [nblk][32][32], written with tag seq
+    // fused loop with a time budget: block 0 publishes here, tagged with seq,
+    // whether the wall clock has passed *deadline (1) or not (0)
+    uint64_t* stop_word;
 };
 
 // Whole compressed outer loop in one launch (Algorithm 1 with the Nesterov
@@ -402,7 +405,9 @@ struct PhaseArgs {
 // seq_pre.  Every workgroup keeps the warm start of lambda_max and the
 // running bound of the global rule itself (every workgroup computes the
 // same values), so the partial products are the only data that cross
-// workgroups between phases.
+// workgroups between phases.  With f.stop_word (a time budget), every
+// workgroup reads block 0's verdict after each F phase and all leave the
+// loop after the same outer iteration.
 struct LoopArgs {
     PhaseArgs g, f;
     int T;

@@ -1346,6 +1346,8 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 a.tol_state[0] = tol / 10.0;
             if (a.done_out) a.done_out[0] = a.done_value;
             if (a.deadline && a.stop_flag && wall_clock64() > *a.deadline) *a.stop_flag = 1;
+            if (a.stop_word)
+                slot_store(a.stop_word, seq, (a.deadline && wall_clock64() > *a.deadline) ? 1u : 0u);
         }
         if (a.tick_out) atomicMax(a.tick_out, (unsigned long long)wall_clock64());
     }
@@ -1441,6 +1443,27 @@ __global__ __launch_bounds__(kThreads) void k_phase_loop(const LoopArgs* __restr
             a.done_value = t + 1;
             asm volatile("" ::: "memory");
             phase_body<PT, TF, DF>(a, blk, L.nbF, a.seq, &sf);
+        }
+        if (L.f.stop_word) {
+            // block 0's verdict after this outer iteration, the same for all
+            // (thread 0 polls; the barrier hands the verdict to the others)
+            const unsigned tag = L.seq0 + 2u * (unsigned)t + 1u;
+            uint64_t w = 0;
+            if (threadIdx.x == 0) {
+                w = slot_load(L.f.stop_word);
+                unsigned spins = 0;
+                while ((unsigned)(w >> 32) != tag) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if ((++spins & 255u) == 0u &&
+                        (spins >= kSpinLimit || (atomic_status_load(&L.g.ctl->status) & CNMF_ST_TIMEOUT))) {
+                        raise_status(L.g.ctl, CNMF_ST_TIMEOUT);
+                        w = 1;   // leave
+                        break;
+                    }
+                    w = slot_load(L.f.stop_word);
+                }
+            }
+            if (__syncthreads_or((int)(w & 1u))) break;
         }
     }
 }
@@ -1562,7 +1585,8 @@ bool phase_loop_supported(int p, int tilesG, int tilesF) {
 hipError_t phase_loop(const Dev& d, const LoopArgs& a, LoopArgs* dev_args, int tilesG, int tilesF) {
     if (!phase_loop_supported(a.g.p, tilesG, tilesF) || a.T < 1 || a.g.mode != 2 || a.f.mode != 2 ||
         a.g.solver != kSolverNesterov || a.f.solver != kSolverNesterov || !a.g.part_in64 ||
-        !a.g.part_out64 || !a.f.part_in64 || !a.f.part_out64 || a.g.stop_flag || a.f.stop_flag)
+        !a.g.part_out64 || !a.f.part_in64 || !a.f.part_out64 || a.g.stop_flag || a.f.stop_flag ||
+        a.g.stop_word || (a.f.stop_word && !a.f.deadline))
         return hipErrorInvalidValue;
     // the argument block goes to device memory ahead of the launch (a copy
     // from pageable memory returns once the source has been read)

@@ -112,31 +112,41 @@ def test_restart_free_running(method):
     assert d_g <= 1e-2
 
 
-def test_time_budget_stops_the_outer_loop():
+@pytest.mark.parametrize("method", ["plain", "compressed"])
+def test_time_budget_stops_the_outer_loop(method):
     """A device-time budget ends the outer loop early: the completed count
     is reported, and the factors are those of an unbudgeted run of that many
-    iterations with the same inner step counts (bitwise)."""
-    say("time_budget")
+    iterations with the same inner step counts (bitwise).  The compressed
+    solve runs its whole loop in one launch, where every workgroup leaves
+    after the outer iteration at whose end workgroup 0 found the deadline
+    passed."""
+    say("time_budget", method)
     import torch
     inst = synth.instance(2000, 2000, 15, 10, seed=1, snr_db=30.0)
     X = dev(inst.X)
-    T = 400
+    comp = None
+    if method == "compressed":
+        comp = cnmf.rsi(X, dev(inst.omega_L), dev(inst.omega_R), 15, 10, 2)
+    T = 400 if comp is None else 2000
+    budget = 2e-3
     G, F = dev(inst.G0), dev(inst.F0)
     tr = cnmf.make_trace(2000, 2000, 15, T, G.device, history=False)
-    cnmf.solve(G, F, X=X, p=15, outer_iters=T, inner_max=100, trace=tr, time_budget=2e-3)
+    cnmf.solve(G, F, X=None if comp else X, compressed=comp, p=15, outer_iters=T, inner_max=100,
+               trace=tr, time_budget=budget)
     cnmf.check()
     done = int(host(tr.outer_done)[0])
     say("outer iterations within 2 ms:", done)
     assert 1 <= done < T
     steps = host(tr.steps).astype(np.int32)[:done]
     G2, F2 = dev(inst.G0), dev(inst.F0)
-    cnmf.solve(G2, F2, X=X, p=15, outer_iters=done, inner_max=100,
-               replay=torch.from_numpy(np.ascontiguousarray(steps)).cuda())
+    cnmf.solve(G2, F2, X=None if comp else X, compressed=comp, p=15, outer_iters=done,
+               inner_max=100, replay=torch.from_numpy(np.ascontiguousarray(steps)).cuda())
     cnmf.check()
     assert np.array_equal(host(G), host(G2)) and np.array_equal(host(F), host(F2))
     # a budget that is not reached changes nothing
     tr2 = cnmf.make_trace(2000, 2000, 15, 5, G.device, history=False)
     G3, F3 = dev(inst.G0), dev(inst.F0)
-    cnmf.solve(G3, F3, X=X, p=15, outer_iters=5, inner_max=100, trace=tr2, time_budget=100.0)
+    cnmf.solve(G3, F3, X=None if comp else X, compressed=comp, p=15, outer_iters=5, inner_max=100,
+               trace=tr2, time_budget=100.0)
     cnmf.check()
     assert int(host(tr2.outer_done)[0]) == 5
