@@ -535,17 +535,22 @@ def bench_adjoint(args, torch, cnmf, synth):
     cos = float(np.sum(gX * rX) / (np.linalg.norm(gX) * np.linalg.norm(rX)))
     rel = float(np.linalg.norm(gX - rX) / np.linalg.norm(rX))
     log(args, "central differences on the GPU forward (32 directions)")
+    # the directions and the FP64 loss sums of the full-size test of this form
     Xh = inst.X.astype(np.float64)
     h = 1e-3
-    fd, an = [], []
+    drng = np.random.default_rng(5)
+    fd, an, flips = [], [], []
     for _ in range(32):
-        D = rng.standard_normal(Xh.shape)
+        D = drng.standard_normal(Xh.shape)
         D *= np.linalg.norm(Xh) / np.linalg.norm(D)
-        vals = []
+        vals, zeros = [], []
         for sgn in (1.0, -1.0):
             G, F, tape = fwd(torch.from_numpy((Xh + sgn * h * D).astype(np.float32)).to(dev))
-            vals.append(float(torch.sum((G - Gtd) ** 2) + torch.sum((F - Ftd) ** 2)))
+            Gd, Fd = G.double(), F.double()
+            vals.append(float(torch.sum((Gd - Gtd.double()) ** 2) + torch.sum((Fd - Ftd.double()) ** 2)))
+            zeros.append(((G == 0).cpu().numpy(), (F == 0).cpu().numpy()))
             tape.close()
+        flips.append(int(np.sum(zeros[0][0] != zeros[1][0]) + np.sum(zeros[0][1] != zeros[1][1])))
         fd.append((vals[0] - vals[1]) / (2 * h))
         an.append(float(np.sum(gX * D)))
     fd, an = np.array(fd), np.array(an)
@@ -559,9 +564,10 @@ def bench_adjoint(args, torch, cnmf, synth):
         "forward_ms": round(min(tf), 3), "backward_ms": round(min(tb), 3),
         "tape_mb": round(tape_bytes / 2 ** 20, 2),
         "vs_fp64_reference": {"cosine": cos, "rel_err": rel, "reference_cpu_s": round(t_ref, 2)},
-        "vs_gpu_central_fd": {"h": h, "directions": 32,
+        "vs_gpu_central_fd": {"h": h, "directions": 32, "loss_sums": "fp64",
                               "cosine": float(fd @ an / (np.linalg.norm(fd) * np.linalg.norm(an))),
-                              "rel_err": float(np.linalg.norm(fd - an) / np.linalg.norm(fd))},
+                              "rel_err": float(np.linalg.norm(fd - an) / np.linalg.norm(fd)),
+                              "flipped_entries_per_direction": flips},
     }
     print(json.dumps(out), flush=True)
 
