@@ -281,8 +281,11 @@ int cnmf_sweep_left(cnmf_ctx* ctx, int64_t R, int64_t C, const float* X,
  * them (one product per chain): Y (R x k, ldy) = X * A with A given as its
  * transpose AT (k x C, row pitch ldat), and Z = X^T * B (B R x k, ldb)
  * written C x k (z_trans = 0) or k x C (z_trans = 1), row pitch ldz.
- * FP32 MFMA, FP32 accumulation, results bitwise reproducible.  R, C >= 1,
- * 1 <= k <= 32; Y and Z must not overlap the inputs. */
+ * FP32 accuracy on the BF16 matrix cores: X, A and B are each split
+ * exactly into three BF16 parts (x = h + m + l) and the six largest cross
+ * products are accumulated in FP32 (the terms left out are below 2^-23 of
+ * |x a|).  Results bitwise reproducible.  R, C >= 1, 1 <= k <= 32; Y and Z
+ * must not overlap the inputs. */
 int cnmf_sweep_dual(cnmf_ctx* ctx, int64_t R, int64_t C, const float* X,
                     int64_t ldx, int32_t k, const float* AT, int64_t ldat,
                     const float* B, int64_t ldb, float* Y, int64_t ldy,

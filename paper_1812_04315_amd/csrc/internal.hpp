@@ -248,6 +248,17 @@ struct TransDesc {
 hipError_t transpose_batched(const Dev& d, const TransDesc* desc, const WorkItem* work,
                              int64_t nwork);
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations (lgkmcnt) but not for its outstanding global loads, so loads
+// issued earlier (a poll of exchange words, the next tile of a stream) stay
+// in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // vmcnt / expcnt untouched, lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
 // reduce_slices: out (rows x k, or k x rows if trans) = sum of S partial
 // slices [S][rows][nt] in slice order (bitwise reproducible).
 hipError_t reduce_slices(const Dev& d, int64_t rows, int k, int64_t S, int nt,

@@ -84,15 +84,6 @@ __device__ __forceinline__ uint64_t slot_load(const uint64_t* p) {
     return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Workgroup barrier for LDS traffic only: waits for this wave's LDS
-// operations (lgkmcnt) but not for its outstanding global loads, so a poll
-// of the exchange words issued earlier stays in flight across it.
-__device__ __forceinline__ void lds_barrier() {
-    __asm__ volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(0xc07f);   // vmcnt / expcnt untouched, lgkmcnt(0)
-    __builtin_amdgcn_s_barrier();
-    __asm__ volatile("" ::: "memory");
-}
 
 // ---------------------------------------------------------------------------
 // lambda_max of a symmetric p x p matrix held in LDS as doubles (destroyed),

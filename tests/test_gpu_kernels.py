@@ -73,6 +73,50 @@ def test_sweep_dual(R, C, k, ld, ldat, z_trans):
     assert np.all(np.abs(Z - X64.T @ B.astype(np.float64)) <= 1e-5 * _bound(X.T, B) + 1e-30)
 
 
+def test_sweep_dual_fp32_accuracy():
+    """The dual pass forms its products from three-way BF16 splits of every
+    FP32 operand (six cross terms on the BF16 matrix cores): its error
+    against the FP64 product stays within a few times that of a plain FP32
+    product of the same operands (torch FP32 matmul on the GPU)."""
+    import torch
+    say("sweep_dual_fp32_accuracy")
+    rng = np.random.default_rng(11)
+    R, C, k = 2000, 3000, 25
+    X = rng.random((R, C)).astype(np.float32)
+    A = rng.standard_normal((C, k)).astype(np.float32)
+    B = rng.standard_normal((R, k)).astype(np.float32)
+    Y, Z = cnmf.sweep_dual(dev(X), dev(A.T.copy()), dev(B))
+    Yt = host(dev(X) @ dev(A))
+    Zt = host(dev(X).T.contiguous() @ dev(B))
+    Y64 = X.astype(np.float64) @ A.astype(np.float64)
+    Z64 = X.T.astype(np.float64) @ B.astype(np.float64)
+    for got, fp32, ref, bound in ((host(Y), Yt, Y64, _bound(X, A)), (host(Z), Zt, Z64, _bound(X.T, B))):
+        e_split = np.max(np.abs(got - ref) / bound)
+        e_fp32 = np.max(np.abs(fp32 - ref) / bound)
+        say("max error / (|X| |A|): split", e_split, "fp32", e_fp32)
+        assert e_split <= 4 * e_fp32 + 1e-9, (e_split, e_fp32)
+
+
+def test_sweep_dual_wide_pitch():
+    """Row pitch of 2^25 + 4 floats (64-bit lane offsets within a group of
+    32 rows), ragged rows and a ragged second column tile; X lives only on
+    the device."""
+    import torch
+    say("sweep_dual_wide_pitch")
+    rng = np.random.default_rng(12)
+    R, C, k, ld = 40, 300, 25, (1 << 25) + 4
+    X = rng.random((R, C)).astype(np.float32)
+    A = rng.standard_normal((C, k)).astype(np.float32)
+    B = rng.standard_normal((R, k)).astype(np.float32)
+    buf = torch.zeros(R, ld, dtype=torch.float32, device="cuda")
+    buf[:, :C] = torch.from_numpy(X).cuda()
+    Y, Z = cnmf.sweep_dual(buf[:, :C], dev(A.T.copy()), dev(B))
+    del buf
+    X64 = X.astype(np.float64)
+    assert np.all(np.abs(host(Y) - X64 @ A.astype(np.float64)) <= 1e-5 * _bound(X, A) + 1e-30)
+    assert np.all(np.abs(host(Z) - X64.T @ B.astype(np.float64)) <= 1e-5 * _bound(X.T, B) + 1e-30)
+
+
 def test_sweep_dual_bitwise_repeatable():
     rng = np.random.default_rng(1)
     X = dev(rng.random((3000, 2000)))
