@@ -277,9 +277,11 @@ def kernel_only(args, cnmf, torch, X, F):
     Bp = torch.randn(n, ell, device=X.device)
     Y = torch.empty(n, ell, device=X.device)
     for name, fn in (("bf16_right_XA", lambda: cnmf.sweep_right_bf16(Xb, AT, a_trans=True, out=Y)),
-                     ("bf16_left_XtB", lambda: cnmf.sweep_left_bf16(Xb, Bp))):
+                     ("bf16_left_XtB", lambda: cnmf.sweep_left_bf16(Xb, Bp)),
+                     ("bf16_dual_XA_XtB", lambda: cnmf.sweep_dual_bf16(Xb, AT, Bp))):
         sec = _timed(torch, fn, args.roofline_reps)
-        byts = 2.0 * n * m + 4.0 * ell * (n + m)
+        dual = "dual" in name
+        byts = 2.0 * n * m + 4.0 * ell * (n + m) * (2 if dual else 1)
         sweeps[name] = {"k": ell, "avg_us": round(sec * 1e6, 2),
                         "achieved_gbs": round(byts / sec / 1e9, 1),
                         "frac": round(byts / sec / 1e9 / HBM_PEAK_GBS, 4),
@@ -449,7 +451,8 @@ def bench_bf16(args, torch, cnmf, synth):
                    ("left_bf16", lambda: cnmf.sweep_left_bf16(X16, Bp)),
                    ("right_fp32", lambda: cnmf.sweep_right(X, AT, a_trans=True, out=Y)),
                    ("left_fp32", lambda: cnmf.sweep_left(X, Bp)),
-                   ("dual_fp32", lambda: cnmf.sweep_dual(X, AT, Bp))):
+                   ("dual_fp32", lambda: cnmf.sweep_dual(X, AT, Bp)),
+                   ("dual_bf16", lambda: cnmf.sweep_dual_bf16(X16, AT, Bp))):
         for _ in range(3):
             f()
         e = _events(torch, 2)

@@ -304,6 +304,21 @@ int cnmf_sweep_left_bf16(cnmf_ctx* ctx, int64_t R, int64_t C, const uint16_t* Xb
                          int64_t ldxb, int32_t k, const float* B, int64_t ldb,
                          float* Z, int64_t ldz, int32_t z_trans);
 
+/* Both BF16 sweeps from one read of Xb (bfloat16 bit patterns, R x C, row
+ * pitch ldxb), as every half-step of Algorithm 2 in the precision form
+ * needs them: Y (R x k, ldy) = Xb * bf16(A) with A given as its transpose
+ * AT (k x C, ldat), and Z = Xb^T * bf16(B) (B R x k, ldb) written C x k
+ * (z_trans = 0) or k x C (z_trans = 1), row pitch ldz.  The skinny operands
+ * are rounded to bfloat16 (nearest even), products accumulate in FP32 on
+ * the matrix cores: the values of cnmf_sweep_right_bf16 and
+ * cnmf_sweep_left_bf16 up to FP32 summation order.  Results bitwise
+ * reproducible.  R, C >= 1, 1 <= k <= 32; Y and Z must not overlap the
+ * inputs. */
+int cnmf_sweep_dual_bf16(cnmf_ctx* ctx, int64_t R, int64_t C, const uint16_t* Xb,
+                         int64_t ldxb, int32_t k, const float* AT, int64_t ldat,
+                         const float* B, int64_t ldb, float* Y, int64_t ldy,
+                         float* Z, int64_t ldz, int32_t z_trans);
+
 /* Orthonormal basis of Y (N x l, ld = l) by CholeskyQR(2) with the rank rule
  * of cnmf_rsi; pool is N x l (pool_trans = 0, ld = l) or l x N
  * (pool_trans = 1, ld = N).  Q out N x l.  replaced out: l int32 flags. */

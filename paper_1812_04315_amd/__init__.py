@@ -35,7 +35,7 @@ EXPORTED = [
     "cnmf_set_stream", "cnmf_clock_hz", "cnmf_status", "cnmf_rsi", "cnmf_rsi_bf16",
     "cnmf_compress",
     "cnmf_to_bf16", "cnmf_solve", "cnmf_solve_noalloc", "cnmf_rre", "cnmf_sweep_right", "cnmf_sweep_left",
-    "cnmf_sweep_dual", "cnmf_sweep_right_bf16", "cnmf_sweep_left_bf16",
+    "cnmf_sweep_dual", "cnmf_sweep_right_bf16", "cnmf_sweep_left_bf16", "cnmf_sweep_dual_bf16",
     "cnmf_orth", "cnmf_lipschitz", "cnmf_nnls",
     "cnmf_batch_create", "cnmf_batch_destroy", "cnmf_batch_rsi", "cnmf_batch_tune",
     "cnmf_batch_solve", "cnmf_adj_forward", "cnmf_adj_backward", "cnmf_tape_bytes",
@@ -117,6 +117,8 @@ def lib() -> ctypes.CDLL:
                                                P, I64, I32]),
             "cnmf_sweep_right_bf16": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, I32, P, I64]),
             "cnmf_sweep_left_bf16": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, P, I64, I32]),
+            "cnmf_sweep_dual_bf16": (ctypes.c_int, [P, I64, I64, P, I64, I32, P, I64, P, I64, P, I64,
+                                                    P, I64, I32]),
             "cnmf_orth": (ctypes.c_int, [P, I64, I32, P, P, I32, D, P, P]),
             "cnmf_lipschitz": (ctypes.c_int, [P, I32, P, P]),
             "cnmf_nnls": (ctypes.c_int, [P, I64, I32, P, I64, I64, P, P, D, I32, I32, I32, P, P, P]),
@@ -495,6 +497,24 @@ def sweep_left_bf16(Xb, B, z_trans: bool = False, out=None):
     _call("cnmf_sweep_left_bf16", context().h, R, C, _ptr(Xb), _ld(Xb), k, _ptr(B), _ld(B),
           _ptr(Z), _ld(Z), 1 if z_trans else 0)
     return Z
+
+
+def sweep_dual_bf16(Xb, AT, B, z_trans: bool = False):
+    """(Y, Z) = (X bf16(A), X^T bf16(B)) from one read of X in bfloat16 (Xb:
+    int16 bit patterns), A given as its transpose AT (k x C), B (R x k)."""
+    torch = _torch()
+    _need(Xb, torch.int16, "Xb", ld_ok=True)
+    _need(AT, torch.float32, "AT", ld_ok=True)
+    _need(B, torch.float32, "B", ld_ok=True)
+    R, C = Xb.shape
+    k = AT.shape[0]
+    if AT.shape[1] != C or B.shape[0] != R or B.shape[1] != k:
+        raise ValueError("inner dimensions differ")
+    Y = torch.empty(R, k, device=Xb.device)
+    Z = torch.empty(k, C, device=Xb.device) if z_trans else torch.empty(C, k, device=Xb.device)
+    _call("cnmf_sweep_dual_bf16", context().h, R, C, _ptr(Xb), _ld(Xb), k, _ptr(AT), _ld(AT),
+          _ptr(B), _ld(B), _ptr(Y), _ld(Y), _ptr(Z), _ld(Z), 1 if z_trans else 0)
+    return Y, Z
 
 
 def orth(Y, pool, pool_trans: bool = False, tau2: float = 1e-9):

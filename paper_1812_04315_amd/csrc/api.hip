@@ -209,6 +209,22 @@ int cnmf_sweep_dual(cnmf_ctx* c, int64_t R, int64_t C, const float* X, int64_t l
                                z_trans != 0, at<float>(c, off)));
 }
 
+int cnmf_sweep_dual_bf16(cnmf_ctx* c, int64_t R, int64_t C, const uint16_t* Xb, int64_t ldxb,
+                         int32_t k, const float* AT, int64_t ldat, const float* B, int64_t ldb,
+                         float* Y, int64_t ldy, float* Z, int64_t ldz, int32_t z_trans) {
+    if (!c || R < 1 || C < 1 || k < 1 || k > 32) return CNMF_EINVAL;
+    if (bad_ptr(Xb) || bad_ptr(AT) || bad_ptr(B) || bad_ptr(Y) || bad_ptr(Z)) return CNMF_EINVAL;
+    if (ldxb < C || ldat < C || ldb < k || ldy < k || (z_trans ? ldz < C : ldz < k))
+        return CNMF_EINVAL;
+    Arena a;
+    size_t off = a.take<float>(sweep_dual_bf16_partial_floats(c->dev, R, C));
+    int rc = ensure_ws(c, a.off);
+    if (rc) return rc;
+    if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
+    return from_hip(sweep_dual_bf16(c->dev, R, C, Xb, ldxb, k, AT, ldat, B, ldb, Y, ldy, Z, ldz,
+                                    z_trans != 0, at<float>(c, off)));
+}
+
 int cnmf_sweep_left(cnmf_ctx* c, int64_t R, int64_t C, const float* X, int64_t ldx, int32_t k,
                     const float* B, int64_t ldb, float* Z, int64_t ldz, int32_t z_trans) {
     if (!c || R < 0 || C < 0 || k < 1 || k > 32) return CNMF_EINVAL;
@@ -336,14 +352,9 @@ int rsi_run(cnmf_ctx* c, int64_t n, int64_t m, const float* X, const uint16_t* X
     const size_t o_oLT = a.take<float>((size_t)l * ldt);
     const size_t o_QRtT = a.take<float>((size_t)l * ldt);
     const size_t o_QLtT = a.take<float>((size_t)l * ldt);
-    size_t part = bf ? std::max(sweep_right_partial_floats(c->dev, n, m),
-                                sweep_left_partial_floats(c->dev, n, m))
-                     : sweep_dual_partial_floats(c->dev, n, m);
-    if (bf)
-        part = std::max(part, std::max(sweep_right_bf16_partial_floats(c->dev, n, m),
-                                       sweep_left_bf16_partial_floats(c->dev, n, m)));
+    const size_t part = bf ? sweep_dual_bf16_partial_floats(c->dev, n, m)
+                           : sweep_dual_partial_floats(c->dev, n, m);
     const size_t o_part = a.take<float>(part);
-    const size_t o_pk = a.take<uint16_t>(bf ? bf16_pack_elems(m) : 1);
     int rc = ensure_ws(c, a.off);
     if (rc) return rc;
     if (hipSetDevice(c->dev.device) != hipSuccess) return CNMF_EHIP;
@@ -357,24 +368,15 @@ int rsi_run(cnmf_ctx* c, int64_t n, int64_t m, const float* X, const uint16_t* X
     float* QRtT = at<float>(c, o_QRtT);
     float* QLtT = at<float>(c, o_QLtT);
     float* pt = at<float>(c, o_part);
-    uint16_t* pk = at<uint16_t>(c, o_pk);
     const double tau2 = prm->tau2;
 
-    // Y (n x l) = X A with A (m x l) given as its transpose AT (l x ldt)
-    auto right = [&](const float* AT, float* Y) -> hipError_t {
-        if (bf) return sweep_right_bf16(d, n, m, Xb, ldx, l, AT, ldt, true, Y, l, pt, pk);
-        return sweep_right(d, n, m, X, ldx, l, AT, ldt, true, Y, l, pt);
-    };
-    auto left = [&](const float* B, float* Z, bool trans) -> hipError_t {  // Z = X^T B
-        const int64_t ldz = trans ? m : l;
-        return sweep_left_bf16(d, n, m, Xb, ldx, l, B, l, Z, ldz, trans, pt);
-    };
-    // Y = X A and Z = X^T B, one product for each chain: FP32 in one read of X
+    // Y (n x l) = X A with A (m x l) given as its transpose AT (l x ldt) and
+    // Z = X^T B, one product for each chain, in one read of X (BF16 form:
+    // X in bfloat16, the skinny operands rounded to bfloat16)
     auto both = [&](const float* AT, float* Y, const float* B, float* Z, bool trans) -> hipError_t {
-        if (bf) {
-            const hipError_t e = right(AT, Y);
-            return e != hipSuccess ? e : left(B, Z, trans);
-        }
+        if (bf)
+            return sweep_dual_bf16(d, n, m, Xb, ldx, l, AT, ldt, B, l, Y, l, Z, trans ? m : l,
+                                   trans, pt);
         return sweep_dual(d, n, m, X, ldx, l, AT, ldt, B, l, Y, l, Z, trans ? m : l, trans, pt);
     };
     // orthonormal bases of an n-space panel Yn_ (n x l, pool Omega_R^T) and an

@@ -199,11 +199,20 @@ hipError_t sweep_left(const Dev& d, int64_t R, int64_t C, const float* X, int64_
                       bool z_trans, float* partial);
 // sweep_dual.hip: Y (R x k, ldy) = X A with A given as its transpose AT
 // (k x C, ldat) and Z = X^T B (B R x k, ldb; Z C x k, or k x C if z_trans)
-// from one read of X; FP32 MFMA, k <= 32 (hipErrorInvalidValue beyond).
+// from one read of X; FP32 accuracy from three-way BF16 splits on the
+// matrix cores, k <= 32 (hipErrorInvalidValue beyond).
 size_t sweep_dual_partial_floats(const Dev& d, int64_t R, int64_t C);
 hipError_t sweep_dual(const Dev& d, int64_t R, int64_t C, const float* X, int64_t ldx, int k,
                       const float* AT, int64_t ldat, const float* B, int64_t ldb, float* Y,
                       int64_t ldy, float* Z, int64_t ldz, bool z_trans, float* partial);
+// The same pair with X in bfloat16 (Xb, row pitch ldx in elements), both
+// skinny operands rounded to bfloat16, FP32 accumulation; partial: workspace
+// of sweep_dual_bf16_partial_floats(d, R, C) floats.
+size_t sweep_dual_bf16_partial_floats(const Dev& d, int64_t R, int64_t C);
+hipError_t sweep_dual_bf16(const Dev& d, int64_t R, int64_t C, const uint16_t* Xb, int64_t ldx,
+                           int k, const float* AT, int64_t ldat, const float* B, int64_t ldb,
+                           float* Y, int64_t ldy, float* Z, int64_t ldz, bool z_trans,
+                           float* partial);
 // Batched sweeps: one descriptor per instance; work items {instance, item}
 // with item = slice * tiles + tile (sweeps), a 256-element chunk of the
 // slice reduction, or a 32 x 32 transpose tile.  X rows and the skinny

@@ -42,6 +42,8 @@ def test_null_context_and_bad_arguments(lib):
     assert lib.cnmf_sweep_left(None, 1, 1, None, 1, 1, None, 1, None, 1, 0) == cnmf.EINVAL
     assert lib.cnmf_sweep_dual(None, 1, 1, None, 1, 1, None, 1, None, 1, None, 1, None, 1,
                                0) == cnmf.EINVAL
+    assert lib.cnmf_sweep_dual_bf16(None, 1, 1, None, 1, 1, None, 1, None, 1, None, 1, None, 1,
+                                    0) == cnmf.EINVAL
     assert lib.cnmf_orth(None, 4, 2, None, None, 0, 1e-9, None, None) == cnmf.EINVAL
     assert lib.cnmf_lipschitz(None, 3, None, None) == cnmf.EINVAL
     prm = cnmf.params(5)

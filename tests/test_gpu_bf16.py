@@ -93,6 +93,41 @@ def test_sweep_left_bf16(R, C, k, ld, z_trans):
     assert np.all(np.abs(Z - ref) <= 1e-5 * _bound(Xv.T, Br) + 1e-30)
 
 
+@pytest.mark.parametrize("R,C,k,ld,ldat,z_trans", [
+    (1, 1, 1, None, None, False), (31, 33, 5, None, None, True), (200, 150, 15, None, 151, False),
+    (257, 1000, 25, 1003, None, True), (1000, 97, 32, 104, 100, False), (64, 4096, 16, None, None, False),
+    (3, 2000, 7, None, 2001, True), (513, 777, 30, 784, 777, False), (2000, 3, 17, None, None, True),
+    (4100, 2304, 25, None, None, False)])
+def test_sweep_dual_bf16(R, C, k, ld, ldat, z_trans):
+    """Both BF16 products of one read of X (every half-step of Algorithm 2
+    in the precision form) against the oracle's emulation: ragged rows and
+    columns, unaligned pitches (ld = 1003: rows not 16-byte aligned), column
+    tiles of 512 and row slices."""
+    say("sweep_dual_bf16", R, C, k, ld, ldat, z_trans)
+    rng = np.random.default_rng(R * 17 + C + k)
+    bits = oracle.bf16_bits(rng.random((R, C)).astype(np.float32))
+    A = rng.standard_normal((C, k)).astype(np.float32)
+    B = rng.standard_normal((R, k)).astype(np.float32)
+    Y, Z = cnmf.sweep_dual_bf16(dev_bits(bits, ld), dev(A.T.copy(), ldat), dev(B), z_trans=z_trans)
+    Y, Z = host(Y), host(Z)
+    if z_trans:
+        Z = Z.T
+    Xv = oracle.bf16_value(bits)
+    Ar, Br = oracle.bf16_round(A), oracle.bf16_round(B)
+    assert np.all(np.abs(Y - Xv @ Ar) <= 1e-5 * _bound(Xv, Ar) + 1e-30)
+    assert np.all(np.abs(Z - Xv.T @ Br) <= 1e-5 * _bound(Xv.T, Br) + 1e-30)
+
+
+def test_sweep_dual_bf16_bitwise_repeatable():
+    rng = np.random.default_rng(2)
+    bits = dev_bits(oracle.bf16_bits(rng.random((3000, 2000)).astype(np.float32)))
+    AT = dev(rng.standard_normal((25, 2000)))
+    B = dev(rng.standard_normal((3000, 25)))
+    a = [host(t) for t in cnmf.sweep_dual_bf16(bits, AT, B)]
+    b = [host(t) for t in cnmf.sweep_dual_bf16(bits, AT, B)]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 def _rsi_bf16(inst, q):
     import torch
     X = dev(inst.X)
