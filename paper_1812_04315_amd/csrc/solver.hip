@@ -605,10 +605,12 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                 sWd[i][j] = 0.5 * ((double)sS[i][j] + (double)sS[j][i]);
             }
         } else {
-            // W = S^T S (l x p -> p x p), FP64 accumulation
+            // W = S^T S (l x p -> p x p), FP64 accumulation in k order
+            // (unrolled so that the LDS reads issue ahead of the chain)
             for (int e = threadIdx.x; e < p * p; e += kThreads) {
                 const int i = e / p, j = e % p;
                 double t = 0.0;
+#pragma unroll 8
                 for (int k = 0; k < a.ell; ++k) t = fma((double)sS[k][i], (double)sS[k][j], t);
                 sW[i][j] = (float)t;
                 sWd[i][j] = (double)(float)t;   // symmetric: (i, j) and (j, i) sum alike
@@ -1316,8 +1318,14 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             const int N = 16 * hn + (l & 15);
             const float s = (sred[0][ri][l] + sred[1][ri][l]) + (sred[2][ri][l] + sred[3][ri][l]);
             const float v = hn < PT ? s : 0.f;
-            if (a.part_out64) slot_store(&a.part_out64[(size_t)blk * 1024 + M * 32 + N], seq, __float_as_uint(v));
-            else a.part_out[(size_t)blk * 1024 + M * 32 + N] = v;
+            // tagged words: only the entries the next phase polls (S is
+            // l x p there); the plain layout is written whole
+            if (a.part_out64) {
+                if (M < (a.mode == 2 ? a.ell : 32) && N < p)
+                    slot_store(&a.part_out64[(size_t)blk * 1024 + M * 32 + N], seq, __float_as_uint(v));
+            } else {
+                a.part_out[(size_t)blk * 1024 + M * 32 + N] = v;
+            }
         }
     }
 
