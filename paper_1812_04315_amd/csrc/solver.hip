@@ -457,7 +457,9 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
     // a time-budgeted loop whose deadline has passed: nothing left to do (the
     // flag was written by an earlier launch, so every workgroup sees it)
     if (a.stop_flag && *a.stop_flag) return;
-    __syncthreads();   // LDS of a previous subproblem on this workgroup
+    // LDS of a previous subproblem on this workgroup (global stores of the
+    // previous phase stay in flight: nothing here reads them back)
+    lds_barrier();
     if constexpr (RESTART)
         for (int e = threadIdx.x; e < kBetaLds; e += kThreads) sbeta[e] = a.beta[e];
     Control* ctl = a.ctl;
@@ -1274,8 +1276,9 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             if (PT == 1)
 #pragma unroll
                 for (int s = 0; s < 4; ++s) zt[wave][q16][16 + 4 * s + g4] = 0.f;
+            // zt[wave] is this wave's own tile: no workgroup barrier (one
+            // would also wait for the iterate's stores just issued)
             __builtin_amdgcn_wave_barrier();
-            __syncthreads();
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int rr = 4 * s + g4;                 // row within the tile (K index)
@@ -1297,7 +1300,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
                     for (int hn = 0; hn < PT; ++hn) acc[hm][hn] = mfma16(av, bv[hn], acc[hm][hn]);
                 }
             }
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
         }
         // reduce the 4 waves: element (M = 16 hm + 4 g4 + i, N = 16 hn + q16)
 #pragma unroll
@@ -1310,7 +1313,7 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
             for (int hn = 0; hn < PT; ++hn)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) sred[wave][(hm * 2 + hn) * 4 + i][lane] = acc[hm][hn][i];
-        __syncthreads();
+        lds_barrier();
         for (int e = threadIdx.x; e < 16 * 64; e += kThreads) {
             const int ri = e / 64, l = e % 64;
             const int hm = (ri / 4) / 2, hn = (ri / 4) % 2, i = ri % 4;
