@@ -64,11 +64,17 @@ __device__ __forceinline__ bool xload(const uint64_t* p, unsigned tag, double* v
     return true;
 }
 
+// Pair e of the upper triangle of a w x w matrix in row order (row a holds
+// (a, a) .. (a, w - 1)): counted from the end, f = T - 1 - e lies in the
+// k-th row from the bottom, k (k + 1) / 2 <= f < (k + 1) (k + 2) / 2.
 __device__ __forceinline__ void pair_of(int e, int w, int* a, int* b) {
-    int rem = e, r = 0;
-    while (rem >= w - r) { rem -= w - r; ++r; }
-    *a = r;
-    *b = r + rem;
+    const int T = w * (w + 1) / 2;
+    const int f = T - 1 - e;
+    int k = (int)((sqrtf(8.f * (float)f + 1.f) - 1.f) * 0.5f);
+    if ((k + 1) * (k + 2) / 2 <= f) ++k;   // float rounding, one step either way
+    if (k * (k + 1) / 2 > f) --k;
+    *a = w - 1 - k;
+    *b = w - 1 - (f - k * (k + 1) / 2);
 }
 
 struct Shared {
@@ -105,21 +111,38 @@ __device__ void gram_partial(const OrthArgs& g, Shared& sh, const float* A, int 
         pb[s] = b;
     }
     const int l = g.l;
-    for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < kTile * w; e += kThreads) {
+    // each thread's elements of a tile (kTile * w <= 8 * kThreads), the next
+    // tile's loaded while the current one is multiplied
+    constexpr int kPer = (kTile * kMaxW + kThreads - 1) / kThreads;
+    float vn[kPer];
+    auto load_tile = [&](int64_t t0) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = threadIdx.x + q * kThreads;
             const int rr = e / w, c = e - rr * w;
             const int64_t r = t0 + rr;
-            double v = 0.0;
-            if (r < r1) v = (c < l) ? (double)A[r * l + c] : (double)g.P[r * g.p_rs + (c - l) * g.p_cs];
-            sh.tile[rr][c] = v;
+            float v = 0.f;
+            if (e < kTile * w && r < r1)
+                v = (c < l) ? A[r * l + c] : g.P[r * g.p_rs + (c - l) * g.p_cs];
+            vn[q] = v;
         }
+    };
+    if (r0 < r1) load_tile(r0);
+    for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            if (e < kTile * w) sh.tile[e / w][e % w] = (double)vn[q];
+        }
+        if (t0 + kTile < r1) load_tile(t0 + kTile);
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < kPairsPerThread; ++s) {
             if (pb[s] >= 0) {
                 double t = acc[s];
-#pragma unroll 2
+                // unrolled so that the LDS reads issue ahead of the chain
+#pragma unroll 8
                 for (int rr = 0; rr < kTile; ++rr) t = fma(sh.tile[rr][pa[s]], sh.tile[rr][pb[s]], t);
                 acc[s] = t;
             }
