@@ -118,6 +118,27 @@ def test_sweep_dual_bf16(R, C, k, ld, ldat, z_trans):
     assert np.all(np.abs(Z - Xv.T @ Br) <= 1e-5 * _bound(Xv.T, Br) + 1e-30)
 
 
+def test_sweep_dual_bf16_wide_pitch():
+    """Row pitch of 2^25 + 8 elements (64-bit lane offsets within a group of
+    32 rows), ragged rows and a ragged second column tile; X lives only on
+    the device."""
+    import torch
+    say("sweep_dual_bf16_wide_pitch")
+    rng = np.random.default_rng(13)
+    R, C, k, ld = 40, 700, 25, (1 << 25) + 8
+    bits = oracle.bf16_bits(rng.random((R, C)).astype(np.float32))
+    A = rng.standard_normal((C, k)).astype(np.float32)
+    B = rng.standard_normal((R, k)).astype(np.float32)
+    buf = torch.zeros(R, ld, dtype=torch.int16, device="cuda")
+    buf[:, :C] = torch.from_numpy(bits.view(np.int16)).cuda()
+    Y, Z = cnmf.sweep_dual_bf16(buf[:, :C], dev(A.T.copy()), dev(B))
+    del buf
+    Xv = oracle.bf16_value(bits)
+    Ar, Br = oracle.bf16_round(A), oracle.bf16_round(B)
+    assert np.all(np.abs(host(Y) - Xv @ Ar) <= 1e-5 * _bound(Xv, Ar) + 1e-30)
+    assert np.all(np.abs(host(Z) - Xv.T @ Br) <= 1e-5 * _bound(Xv.T, Br) + 1e-30)
+
+
 def test_sweep_dual_bf16_bitwise_repeatable():
     rng = np.random.default_rng(2)
     bits = dev_bits(oracle.bf16_bits(rng.random((3000, 2000)).astype(np.float32)))
