@@ -43,7 +43,12 @@ constexpr int kMaxW = 64;        // augmented width 2 l
 constexpr int kMaxPairs = kOrthMaxPairs;   // pairs of a 64-column Gram
 constexpr int kPairsPerThread = (kMaxPairs + kThreads - 1) / kThreads;   // 9
 constexpr int kTile = 32;
+constexpr int kGramBlocksPerWave = 3;   // ceil(10 upper 16 x 16 blocks of a 64-column Gram / 4 waves)
 constexpr double kPolish = 1e-7;   // min pivot ratio below which pass 2 runs
+
+// accumulator of one 16 x 16 FP64 matrix-core product: register i of lane t
+// holds row 4 i + t / 16, column t mod 16
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void xstore(uint64_t* p, unsigned tag, double v) {
     const uint64_t bits = (uint64_t)__double_as_longlong(v);
@@ -97,13 +102,17 @@ namespace {
 
 // Gram partial over this workgroup's rows: pairs (a <= b) of the w columns of
 // [A | P] (w = l: only A).  A element (r, c) at A[r * l + c].
+// Tiles of 32 rows are staged in LDS as FP64 (the next tile's loads in flight
+// while the current one is multiplied).  The Gram's upper 16 x 16 blocks
+// (at most 10 for w <= 64) go round-robin to the four waves, each a tile^T
+// tile product on the FP64 matrix cores, K = rows in steps of 4.  At the end
+// the blocks pass through sh.M into the per-thread pair accumulators.
 __device__ void gram_partial(const OrthArgs& g, Shared& sh, const float* A, int w, int64_t r0,
                              int64_t r1, double (&acc)[kPairsPerThread], int (&pa)[kPairsPerThread],
                              int (&pb)[kPairsPerThread]) {
     const int npairs = w * (w + 1) / 2;
 #pragma unroll
     for (int s = 0; s < kPairsPerThread; ++s) {
-        acc[s] = 0.0;
         const int e = threadIdx.x + s * kThreads;
         int a = 0, b = -1;
         if (e < npairs) pair_of(e, w, &a, &b);
@@ -111,8 +120,22 @@ __device__ void gram_partial(const OrthArgs& g, Shared& sh, const float* A, int 
         pb[s] = b;
     }
     const int l = g.l;
-    // each thread's elements of a tile (kTile * w <= 8 * kThreads), the next
-    // tile's loaded while the current one is multiplied
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    // this wave's blocks (at, bt), at <= bt < nb, counted in row order
+    const int nb = (w + 15) >> 4, nblocks = nb * (nb + 1) / 2;
+    int bat[kGramBlocksPerWave], bbt[kGramBlocksPerWave];
+#pragma unroll
+    for (int u = 0; u < kGramBlocksPerWave; ++u) {
+        int j = wave + 4 * u, at = 0;
+        while (at < nb && j >= nb - at) { j -= nb - at; ++at; }
+        bat[u] = at;
+        bbt[u] = at + j;   // valid when wave + 4 u < nblocks
+    }
+    v4d gacc[kGramBlocksPerWave];
+#pragma unroll
+    for (int u = 0; u < kGramBlocksPerWave; ++u) gacc[u] = (v4d){0.0, 0.0, 0.0, 0.0};
+    // each thread's elements of a tile (kTile * w <= 8 * kThreads)
     constexpr int kPer = (kTile * kMaxW + kThreads - 1) / kThreads;
     float vn[kPer];
     auto load_tile = [&](int64_t t0) {
@@ -129,25 +152,39 @@ __device__ void gram_partial(const OrthArgs& g, Shared& sh, const float* A, int 
     };
     if (r0 < r1) load_tile(r0);
     for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
-        __syncthreads();
+        lds_barrier();   // every wave is done with the previous tile
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int e = threadIdx.x + q * kThreads;
             if (e < kTile * w) sh.tile[e / w][e % w] = (double)vn[q];
         }
         if (t0 + kTile < r1) load_tile(t0 + kTile);
-        __syncthreads();
+        lds_barrier();   // LDS only: the loads above stay in flight
 #pragma unroll
-        for (int s = 0; s < kPairsPerThread; ++s) {
-            if (pb[s] >= 0) {
-                double t = acc[s];
-                // unrolled so that the LDS reads issue ahead of the chain
-#pragma unroll 8
-                for (int rr = 0; rr < kTile; ++rr) t = fma(sh.tile[rr][pa[s]], sh.tile[rr][pb[s]], t);
-                acc[s] = t;
+        for (int u = 0; u < kGramBlocksPerWave; ++u) {
+            if (wave + 4 * u < nblocks) {
+                const int ca = 16 * bat[u] + li, cb = 16 * bbt[u] + li;
+#pragma unroll
+                for (int s = 0; s < kTile / 4; ++s) {
+                    const int rr = 4 * s + lk;
+                    const double x = ca < w ? sh.tile[rr][ca] : 0.0;
+                    const double y = cb < w ? sh.tile[rr][cb] : 0.0;
+                    gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, gacc[u], 0, 0, 0);
+                }
             }
         }
     }
+    // block element (4 i + lk, li) of register i -> sh.M, then the pairs
+#pragma unroll
+    for (int u = 0; u < kGramBlocksPerWave; ++u) {
+        if (wave + 4 * u < nblocks) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sh.M[16 * bat[u] + 4 * i + lk][16 * bbt[u] + li] = gacc[u][i];
+        }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int s = 0; s < kPairsPerThread; ++s) acc[s] = pb[s] >= 0 ? sh.M[pa[s]][pb[s]] : 0.0;
 }
 
 // Sum of the partial Grams over the grid -> sh.M (full symmetric, w x w).
@@ -397,30 +434,67 @@ __device__ void cholesky_wave(const OrthArgs& g, Shared& sh, int w, bool allow_s
 }
 
 // Q[r][:] = Ysrc^[r][:] * Ri over this workgroup's rows (FP64 arithmetic):
-// tiles of 32 rows staged in LDS, one output element per thread and step.
+// tiles of 32 rows staged in LDS (the next tile's loads in flight while the
+// current one is multiplied).  Wave (mt, nt) forms the 16 x 16 block of rows
+// 16 mt.., columns 16 nt.. of tile * Ri on the FP64 matrix cores, K in steps
+// of 4 (Ri is zero below its diagonal; entries past row or column l are
+// masked), and, for QT, the transposed block Ri^T tile^T from the same
+// operands, whose lanes then hold 16 consecutive rows of one QT column.
 __device__ void apply_rows(const OrthArgs& g, Shared& sh, const float* Ysrc, bool use_pool,
                            int64_t r0, int64_t r1, float* Qdst, float* QT) {
     const int l = g.l;
-    for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < kTile * l; e += kThreads) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int mt = wave & 1, nt = wave >> 1;
+    const int c = 16 * nt + li;          // B operand and Q output column
+    const bool active = 16 * nt < l;     // wave-uniform
+    constexpr int kPer = (kTile * 32 + kThreads - 1) / kThreads;   // kTile * l <= 4 * kThreads
+    float vn[kPer];
+    auto load_tile = [&](int64_t t0) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = threadIdx.x + q * kThreads;
             const int rr = e / l, i = e - rr * l;
             const int64_t r = t0 + rr;
-            double v = 0.0;
-            if (r < r1)
-                v = (use_pool && sh.sel[i]) ? (double)g.P[r * g.p_rs + i * g.p_cs]
-                                            : (double)Ysrc[r * l + i];
-            sh.tile[rr][i] = v;
+            float v = 0.f;
+            if (e < kTile * l && r < r1)
+                v = (use_pool && sh.sel[i]) ? g.P[r * g.p_rs + i * g.p_cs] : Ysrc[r * l + i];
+            vn[q] = v;
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < kTile * l; e += kThreads) {
-            const int rr = e / l, c = e - rr * l;
-            const int64_t r = t0 + rr;
-            if (r < r1) {
-                double s = 0.0;
-                for (int i = 0; i <= c; ++i) s = fma(sh.tile[rr][i], sh.Ri[i][c], s);
-                Qdst[r * l + c] = (float)s;
-                if (QT) QT[(int64_t)c * g.ldqt + r] = (float)s;
+    };
+    if (r0 < r1) load_tile(r0);
+    for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
+        lds_barrier();   // every wave is done with the previous tile
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = threadIdx.x + q * kThreads;
+            if (e < kTile * l) sh.tile[e / l][e % l] = (double)vn[q];
+        }
+        if (t0 + kTile < r1) load_tile(t0 + kTile);
+        lds_barrier();   // LDS only: the loads above and the last stores stay in flight
+        if (!active) continue;
+        v4d d = {0.0, 0.0, 0.0, 0.0}, dt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int k = 4 * s + lk;
+            const double a = k < l ? sh.tile[16 * mt + li][k] : 0.0;
+            const double b = (k < l && c < l) ? sh.Ri[k][c] : 0.0;
+            d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+            if (QT) dt = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, dt, 0, 0, 0);
+        }
+        // d: register i holds row 16 mt + 4 i + lk, column c;
+        // dt: register i holds column 16 nt + 4 i + lk, row 16 mt + li
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = t0 + 16 * mt + 4 * i + lk;
+            if (r < r1 && c < l) Qdst[r * l + c] = (float)d[i];
+        }
+        if (QT) {
+            const int64_t r = t0 + 16 * mt + li;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int col = 16 * nt + 4 * i + lk;
+                if (r < r1 && col < l) QT[(int64_t)col * g.ldqt + r] = (float)dt[i];
             }
         }
     }

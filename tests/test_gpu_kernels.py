@@ -141,7 +141,10 @@ def test_sweep_bitwise_repeatable():
     assert np.array_equal(host(cnmf.sweep_left(X, B)), host(cnmf.sweep_left(X, B)))
 
 
-@pytest.mark.parametrize("N,ell", [(40, 1), (200, 15), (1000, 25), (3001, 32), (32, 32)])
+# 40000 and 70001 rows give every workgroup more rows than one staged slab
+# (two and three slabs, the last ragged)
+@pytest.mark.parametrize("N,ell", [(40, 1), (200, 15), (1000, 25), (3001, 32), (32, 32),
+                                   (40000, 25), (70001, 32)])
 def test_orth_full_rank(N, ell):
     say("orth_full_rank", N, ell)
     rng = np.random.default_rng(N + ell)
@@ -176,11 +179,14 @@ def test_orth_nearly_collinear_columns(delta, tau2):
     assert np.linalg.norm(Y64 - Qh @ (Qh.T @ Y64)) <= 1e-5 * np.linalg.norm(Y64)
 
 
+# (3000, 20): the augmented Gram has 40 columns and each workgroup's rows fit
+# one slab; (25600, 20): about 100 rows per workgroup, more than one slab of
+# the augmented Gram
+@pytest.mark.parametrize("N,ell,r", [(300, 12, 5), (3000, 20, 8), (25600, 20, 8)])
 @pytest.mark.parametrize("pool_trans", [False, True])
-def test_orth_rank_deficient(pool_trans):
-    say("orth_rank_deficient", pool_trans)
+def test_orth_rank_deficient(pool_trans, N, ell, r):
+    say("orth_rank_deficient", pool_trans, N, ell, r)
     rng = np.random.default_rng(3)
-    N, ell, r = 300, 12, 5
     Y = (rng.random((N, r)) @ rng.random((r, ell))).astype(np.float32)
     Y[:, 7] = 0.0
     P = rng.standard_normal((N, ell)).astype(np.float32)
