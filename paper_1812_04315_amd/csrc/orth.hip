@@ -95,6 +95,26 @@ struct Shared {
     int timeout;
 };
 
+// (row, column) of element e = threadIdx.x + kThreads q of a row-major tile
+// with w columns, without a division per element: stepping e by
+// kThreads = A w + B moves A rows and B columns, with at most one carry.
+template <int N>
+__device__ __forceinline__ void tile_coords(int w, int (&er)[N], int (&ec)[N]) {
+    const int A = kThreads / w, B = kThreads - A * w;
+    int rr = (int)threadIdx.x / w, c = (int)threadIdx.x - rr * w;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        er[q] = rr;
+        ec[q] = c;
+        c += B;
+        rr += A;
+        if (c >= w) {
+            c -= w;
+            ++rr;
+        }
+    }
+}
+
 }  // namespace
 
 
@@ -110,6 +130,25 @@ namespace {
 __device__ void gram_partial(const OrthArgs& g, Shared& sh, const float* A, int w, int64_t r0,
                              int64_t r1, double (&acc)[kPairsPerThread], int (&pa)[kPairsPerThread],
                              int (&pb)[kPairsPerThread]) {
+    const int l = g.l;
+    // each thread's elements of a tile (kTile * w <= 8 * kThreads); the first
+    // tile's loads go out before the index set-up below
+    constexpr int kPer = (kTile * kMaxW + kThreads - 1) / kThreads;
+    float vn[kPer];
+    int er[kPer], ec[kPer];
+    tile_coords(w, er, ec);
+    auto load_tile = [&](int64_t t0) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int rr = er[q], c = ec[q];
+            const int64_t r = t0 + rr;
+            float v = 0.f;
+            if (rr < kTile && r < r1)
+                v = (c < l) ? A[r * l + c] : g.P[r * g.p_rs + (c - l) * g.p_cs];
+            vn[q] = v;
+        }
+    };
+    if (r0 < r1) load_tile(r0);
     const int npairs = w * (w + 1) / 2;
 #pragma unroll
     for (int s = 0; s < kPairsPerThread; ++s) {
@@ -119,7 +158,6 @@ __device__ void gram_partial(const OrthArgs& g, Shared& sh, const float* A, int 
         pa[s] = a;
         pb[s] = b;
     }
-    const int l = g.l;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     // this wave's blocks (at, bt), at <= bt < nb, counted in row order
@@ -135,29 +173,11 @@ __device__ void gram_partial(const OrthArgs& g, Shared& sh, const float* A, int 
     v4d gacc[kGramBlocksPerWave];
 #pragma unroll
     for (int u = 0; u < kGramBlocksPerWave; ++u) gacc[u] = (v4d){0.0, 0.0, 0.0, 0.0};
-    // each thread's elements of a tile (kTile * w <= 8 * kThreads)
-    constexpr int kPer = (kTile * kMaxW + kThreads - 1) / kThreads;
-    float vn[kPer];
-    auto load_tile = [&](int64_t t0) {
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int e = threadIdx.x + q * kThreads;
-            const int rr = e / w, c = e - rr * w;
-            const int64_t r = t0 + rr;
-            float v = 0.f;
-            if (e < kTile * w && r < r1)
-                v = (c < l) ? A[r * l + c] : g.P[r * g.p_rs + (c - l) * g.p_cs];
-            vn[q] = v;
-        }
-    };
-    if (r0 < r1) load_tile(r0);
     for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
         lds_barrier();   // every wave is done with the previous tile
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int e = threadIdx.x + q * kThreads;
-            if (e < kTile * w) sh.tile[e / w][e % w] = (double)vn[q];
-        }
+        for (int q = 0; q < kPer; ++q)
+            if (er[q] < kTile) sh.tile[er[q]][ec[q]] = (double)vn[q];
         if (t0 + kTile < r1) load_tile(t0 + kTile);
         lds_barrier();   // LDS only: the loads above stay in flight
 #pragma unroll
@@ -259,45 +279,70 @@ __device__ bool gram_exchange(const OrthArgs& g, Shared& sh, int w, unsigned tag
     return true;
 }
 
-// R^-1 of the upper-triangular R held in sh.M[0..l-1][0..l-1] into sh.Ri, by
-// one wavefront: lane c owns column c in registers and back-substitutes
-// x_i = -(sum_{t > i} R[i][t] x_t) / R[i][i], x_c = 1 / R[c][c]; rows of R
-// are broadcast reads from LDS.  Fully unrolled (register indices are
-// compile-time constants).
+// R^-1 of the upper-triangular R held in sh.M[0..l-1][0..l-1] into sh.Ri
+// (zero below the diagonal), by one wavefront, in 16 x 16 blocks
+// R = [R11 R12; 0 R22]: lanes 0..15 back-substitute the columns of R11^-1 and
+// lanes 16..31 those of R22^-1 in the same instructions (within a block,
+// x_i = -(sum_{t > i} R_it x_t) / R_ii below the diagonal entry
+// x_c = 1 / R_cc; rows of the block are broadcast reads from LDS, x is held
+// in registers), then the corner -R11^-1 (R12 R22^-1) comes from two 16 x 16
+// products on the FP64 matrix cores, the first staged through sh.tile.
+// Rows and columns past l act as the identity.
 __device__ void inverse_upper(Shared& sh, int l) {
-    const int c = threadIdx.x;
-    if (c < l) sh.dinv[c] = 1.0 / sh.M[c][c];
+    const int lane = threadIdx.x;   // wave 0, all lanes (the products need the full wave)
+    if (lane < 32) sh.dinv[lane] = lane < l ? 1.0 / sh.M[lane][lane] : 1.0;
     __builtin_amdgcn_wave_barrier();
-    double x[32];
+    if (lane < 32) {
+        const int o = lane & 16, cc = lane & 15;   // block offset, column within it
+        double x[16];
 #pragma unroll
-    for (int i = 0; i < 32; ++i) x[i] = 0.0;
+        for (int i = 0; i < 16; ++i) x[i] = 0.0;
 #pragma unroll
-    for (int i = 31; i >= 0; --i) {
-        if (i < l) {
+        for (int i = 15; i >= 0; --i) {
             double s = 0.0;
 #pragma unroll
-            for (int t = i + 1; t < 32; ++t) {
-                const double r = sh.M[i][t];
-                s = fma(t < l ? r : 0.0, x[t], s);
+            for (int t = i + 1; t < 16; ++t) {
+                const double r = sh.M[o + i][o + t];
+                s = fma(o + t < l ? r : 0.0, x[t], s);
             }
-            const double di = sh.dinv[i];
-            x[i] = (i == c) ? di : (i < c ? -s * di : 0.0);
+            const double di = sh.dinv[o + i];
+            x[i] = (i == cc) ? di : (i < cc ? -s * di : 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sh.Ri[o + i][o + cc] = x[i];
+        if (o == 0) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) sh.Ri[16 + i][cc] = 0.0;   // below R11^-1
         }
     }
-    if (c < l) {
+    __builtin_amdgcn_wave_barrier();
+    if (l > 16) {   // uniform
+        const int li = lane & 15, lk = lane >> 4;
+        // P = R12 R22^-1, K = 16 in steps of 4
+        v4d pp = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int t = 0; t < 32; ++t)
-            if (t < l) sh.Ri[t][c] = x[t];
+        for (int s = 0; s < 4; ++s) {
+            const int k = 4 * s + lk;
+            const double a = 16 + k < l ? sh.M[li][16 + k] : 0.0;
+            const double b = sh.Ri[16 + k][16 + li];
+            pp = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, pp, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sh.tile[4 * i + lk][li] = pp[i];
+        __builtin_amdgcn_wave_barrier();
+        // corner = -R11^-1 P
+        v4d xc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = 4 * s + lk;
+            xc = __builtin_amdgcn_mfma_f64_16x16x4f64(sh.Ri[li][k], sh.tile[k][li], xc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sh.Ri[4 * i + lk][16 + li] = -xc[i];
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-// Right-looking Cholesky of the l x l Gram in sh.M by one wavefront with the
-// matrix in registers (lane i holds row i, which is also column i of the
-// symmetric trailing part); fully unrolled.  detect: a pivot failing the
-// rank rule sets sh.flag and returns (the caller switches to the augmented
-// Gram); otherwise a pivot <= tau2 * W_jj is a breakdown (pivot set to 1 and
-// the column zeroed).  R is left in sh.M (row j = R[j][.]), R^-1 in sh.Ri.
 __device__ void cholesky_regs(const OrthArgs& g, Shared& sh, bool detect) {
     const int lane = threadIdx.x;   // wave 0 only
     const int l = g.l;
@@ -450,14 +495,15 @@ __device__ void apply_rows(const OrthArgs& g, Shared& sh, const float* Ysrc, boo
     const bool active = 16 * nt < l;     // wave-uniform
     constexpr int kPer = (kTile * 32 + kThreads - 1) / kThreads;   // kTile * l <= 4 * kThreads
     float vn[kPer];
+    int er[kPer], ec[kPer];
+    tile_coords(l, er, ec);
     auto load_tile = [&](int64_t t0) {
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
-            const int e = threadIdx.x + q * kThreads;
-            const int rr = e / l, i = e - rr * l;
+            const int rr = er[q], i = ec[q];
             const int64_t r = t0 + rr;
             float v = 0.f;
-            if (e < kTile * l && r < r1)
+            if (rr < kTile && r < r1)
                 v = (use_pool && sh.sel[i]) ? g.P[r * g.p_rs + i * g.p_cs] : Ysrc[r * l + i];
             vn[q] = v;
         }
@@ -466,10 +512,8 @@ __device__ void apply_rows(const OrthArgs& g, Shared& sh, const float* Ysrc, boo
     for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
         lds_barrier();   // every wave is done with the previous tile
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int e = threadIdx.x + q * kThreads;
-            if (e < kTile * l) sh.tile[e / l][e % l] = (double)vn[q];
-        }
+        for (int q = 0; q < kPer; ++q)
+            if (er[q] < kTile) sh.tile[er[q]][ec[q]] = (double)vn[q];
         if (t0 + kTile < r1) load_tile(t0 + kTile);
         lds_barrier();   // LDS only: the loads above and the last stores stay in flight
         if (!active) continue;

@@ -615,7 +615,10 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, const unsigned bl
 #pragma unroll 8
                 for (int k = 0; k < a.ell; ++k) t = fma((double)sS[k][i], (double)sS[k][j], t);
                 sW[i][j] = (float)t;
-                sWd[i][j] = (double)(float)t;   // symmetric: (i, j) and (j, i) sum alike
+                // lambda_max is taken of the FP32 W that the gradient uses (its
+                // Lipschitz constant), held exactly in FP64; symmetric: (i, j)
+                // and (j, i) sum alike
+                sWd[i][j] = (double)(float)t;
             }
         }
     }
