@@ -141,10 +141,11 @@ def test_sweep_bitwise_repeatable():
     assert np.array_equal(host(cnmf.sweep_left(X, B)), host(cnmf.sweep_left(X, B)))
 
 
-# 40000 and 70001 rows give every workgroup more rows than one staged slab
-# (two and three slabs, the last ragged)
+# 40000 and 70001 rows give every workgroup several 32-row tiles (the last
+# ragged); 16 and 17 columns sit either side of the 16-column blocks of the
+# matrix-core products (R^-1's corner block, Q's second column block)
 @pytest.mark.parametrize("N,ell", [(40, 1), (200, 15), (1000, 25), (3001, 32), (32, 32),
-                                   (40000, 25), (70001, 32)])
+                                   (40000, 25), (70001, 32), (3000, 16), (3000, 17)])
 def test_orth_full_rank(N, ell):
     say("orth_full_rank", N, ell)
     rng = np.random.default_rng(N + ell)
@@ -179,10 +180,11 @@ def test_orth_nearly_collinear_columns(delta, tau2):
     assert np.linalg.norm(Y64 - Qh @ (Qh.T @ Y64)) <= 1e-5 * np.linalg.norm(Y64)
 
 
-# (3000, 20): the augmented Gram has 40 columns and each workgroup's rows fit
-# one slab; (25600, 20): about 100 rows per workgroup, more than one slab of
-# the augmented Gram
-@pytest.mark.parametrize("N,ell,r", [(300, 12, 5), (3000, 20, 8), (25600, 20, 8)])
+# The augmented Gram [Y P] has 2 ell columns: 24 (two 16-column blocks), 40
+# (three) and 64 (four: ten upper blocks, three on some waves); 3000 rows give
+# one 32-row tile per workgroup, 25600 and 40000 several
+@pytest.mark.parametrize("N,ell,r", [(300, 12, 5), (3000, 20, 8), (25600, 20, 8),
+                                     (3000, 32, 10), (40000, 32, 10)])
 @pytest.mark.parametrize("pool_trans", [False, True])
 def test_orth_rank_deficient(pool_trans, N, ell, r):
     say("orth_rank_deficient", pool_trans, N, ell, r)
